@@ -1,0 +1,141 @@
+/*
+ * median_filter.h -- C ABI of the MI355X (gfx950) exact median-filter library.
+ *
+ * Method: B. Weiss, "Fast Isotropic Median Filtering" (SIGGRAPH 2025).  The
+ * library filters an image with a disc, ellipse or convex-polygon window and
+ * returns, for every pixel, the element of zero-based rank (N-1)/2 of the N
+ * window values (section "Core concepts: Histograms, Pivots, and Counts":
+ * for a 7x7 window, the 25th of 49).  The result is exact: it is always one
+ * of the input values, bit for bit.  It is computed per tile with the
+ * ordinal transform, the omnigram and pivot/count sliding (sections "The
+ * Omnigram", "Method Summary", "Implementation" and "GPU").
+ *
+ * Conventions shared by every entry point
+ *  - Image and output buffers are DEVICE pointers owned by the caller.  They
+ *    are single-plane, row-major, with the same row stride in bytes; the
+ *    stride must be >= w * element size and a multiple of the element size.
+ *    Multi-channel (planar) images are filtered one plane per call or per
+ *    batch entry.
+ *  - Offsets are (dx, dy) with dx to the right and dy down the rows.
+ *  - Pixels outside the image are taken from inside by the boundary rule:
+ *    MF_CLAMP repeats the edge pixel; MF_MIRROR reflects about the edge pixel
+ *    without repeating it (index -1 -> 1, w -> w-2), folding again as often
+ *    as needed, so any radius is legal for any image size (w == 1 mirrors to
+ *    index 0).
+ *  - float32 values are ordered by IEEE 754 totalOrder: -0 < +0, and NaNs of
+ *    either sign sort beyond the infinities of that sign.
+ *  - Calls are asynchronous on `stream` (0 = the null stream).  Argument
+ *    errors are returned before anything is queued; launch errors come back
+ *    as MF_ERR_HIP.  No C++ exception crosses this interface.
+ *  - `out` must not overlap `img` (MF_ERR_ALIAS): tiles read their
+ *    neighbours' halo pixels while other tiles write.
+ *  - w == 0 or h == 0 is a successful no-op.
+ */
+#ifndef MEDIAN_FILTER_H
+#define MEDIAN_FILTER_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;
+
+typedef enum { MF_U8 = 0, MF_U16 = 1, MF_F32 = 2 } mf_dtype;
+typedef enum { MF_CLAMP = 0, MF_MIRROR = 1 } mf_boundary;
+typedef enum {
+  MF_OK = 0,
+  MF_ERR_INVALID_ARG = -1, /* null pointer, bad size/stride/enum value          */
+  MF_ERR_ALIAS = -2,       /* out overlaps img                                   */
+  MF_ERR_UNSUPPORTED = -3, /* footprint not row- and column-convex, or too big   */
+  MF_ERR_NOMEM = -4,       /* device or host allocation failed                   */
+  MF_ERR_HIP = -5          /* a HIP runtime call or kernel launch failed         */
+} mf_status;
+
+/* Human-readable name of a status code (static storage; never NULL). */
+const char* mf_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Footprints (paper, Eq. 3 and "Arbitrary Convex Kernel Shapes").
+ *
+ * A footprint is an immutable host object owned by the caller.  It is
+ * rasterised once into integer row spans; the GPU never evaluates geometry.
+ * It must be row- and column-convex (each row and column of the window is
+ * one run of pixels), which holds for every convex shape; the constructors
+ * return MF_ERR_UNSUPPORTED otherwise.  Its extent is limited to 255 pixels
+ * in each direction from the centre.  The library uploads the spans to each
+ * device the first time the footprint is used there and keeps that copy
+ * until mf_footprint_destroy.
+ * ------------------------------------------------------------------------ */
+typedef struct mf_footprint mf_footprint;
+
+/* Disc of radius r: offsets with dx^2 + dy^2 <= r^2 (Eq. 3). r >= 0. */
+int mf_footprint_disc(int r, mf_footprint** out);
+
+/* Disc with an explicit squared limit: dx^2 + dy^2 <= limit.  limit = r(r+1)
+ * gives the sets the paper's figures count (21 taps at radius 2). */
+int mf_footprint_disc_limit(long long limit, mf_footprint** out);
+
+/* Ellipse with semi-axes a, b (> 0) rotated by theta_deg (+x turns towards
+ * +dy).  Member iff (u/a)^2 + (v/b)^2 <= 1 + 1e-9, u = dx cos + dy sin,
+ * v = -dx sin + dy cos: lattice points on the boundary are members. */
+int mf_footprint_ellipse(double a, double b, double theta_deg, mf_footprint** out);
+
+/* Convex polygon from n_vertices (x, y) pairs in `xy`, either winding;
+ * inclusive: points within 1e-9 * (max vertex radius) of an edge are members. */
+int mf_footprint_polygon(const double* xy, int n_vertices, mf_footprint** out);
+
+/* Regular polygon: vertices at angles rot_deg + 360 k / n_sides on a circle
+ * of radius `circumradius` (a vertex on +x when rot_deg == 0). */
+int mf_footprint_regular_polygon(int n_sides, double circumradius, double rot_deg,
+                                 mf_footprint** out);
+
+/* Tap count N, median rank (N-1)/2 and bounding offsets.  Any output
+ * pointer may be NULL. */
+int mf_footprint_info(const mf_footprint* fp, int* taps, int* rank, int* dx_min,
+                      int* dx_max, int* dy_min, int* dy_max);
+
+/* Host copy of the row spans: for row dy = dy_min + i, the window holds
+ * dx in [x_lo[i], x_hi[i]].  Arrays have dy_max - dy_min + 1 entries. */
+int mf_footprint_row_spans(const mf_footprint* fp, int* x_lo, int* x_hi);
+
+void mf_footprint_destroy(mf_footprint* fp);
+
+/* ------------------------------------------------------------------------
+ * Plain filter (paper, "Method Summary" steps 1-5 and 7; "GPU").
+ *
+ * Filters one plane: out(x, y) = rank-(N-1)/2 element of the window values
+ * around (x, y).  img/out: device pointers, stride_bytes as above; dtype is
+ * an mf_dtype and boundary an mf_boundary.  Scratch memory, if the chosen
+ * tiling needs it, is allocated by the library on first use per device and
+ * kept for later calls.
+ * ------------------------------------------------------------------------ */
+int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                  const mf_footprint* fp, int boundary, void* out, hipStream_t stream);
+
+/* As median_filter, with an explicit zero-based rank in [0, N) instead of
+ * the median: a percentile filter (paper, Conclusion and the percentile
+ * figures of the appendix). */
+int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                       const mf_footprint* fp, int boundary, int rank, void* out,
+                       hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Tile-shape control, for measurement and tuning.  tile_w/tile_h are the
+ * output tile size (multiples of 8, 8..64 wide); 0 restores the automatic
+ * choice.  Affects later calls from every thread.
+ * ------------------------------------------------------------------------ */
+int mf_set_tile_override(int tile_w, int tile_h);
+
+/* The tile shape and launch the plain filter would use for this image and
+ * footprint: output tile size, input box size (tile + window extent) and
+ * the LDS bytes per workgroup.  Host-only; runs no GPU code. */
+int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, int* tile_h,
+                  int* box_w, int* box_h, int* lds_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEDIAN_FILTER_H */

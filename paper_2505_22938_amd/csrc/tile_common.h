@@ -1,0 +1,160 @@
+// Device-side building blocks shared by the plain, batched and learned
+// kernels: boundary remap, key transform, tile load and the per-tile LDS
+// radix sort that produces the reverse map C and the omnigram.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+enum { KEY_U8 = 0, KEY_U16 = 1, KEY_F32 = 2 };
+enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };
+
+constexpr int kThreads = 1024;            // threads per tile workgroup
+constexpr int kWaves = kThreads / 64;     // wave64
+constexpr int kDigits = 16;               // 4-bit radix digits
+constexpr int kCounterBytes = kDigits * kThreads * 2;
+
+// Boundary rule: clamp repeats the edge pixel; mirror reflects about it
+// without repeating it and folds with period 2(n-1).
+__device__ __forceinline__ int remap(int x, int n, int boundary) {
+  if ((unsigned)x < (unsigned)n) return x;
+  if (boundary == 0) return x < 0 ? 0 : n - 1;
+  if (n == 1) return 0;
+  const int period = 2 * (n - 1);
+  int m = x % period;
+  if (m < 0) m += period;
+  return m >= n ? period - m : m;
+}
+
+// float32 bits -> unsigned key whose unsigned order is IEEE totalOrder
+// (paper, "Implementation": XOR exponent and mantissa by the sign bit and
+// flip the sign bit).  key_to_f32 inverts it.
+__device__ __forceinline__ uint32_t f32_to_key(uint32_t b) {
+  return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ uint32_t key_to_f32(uint32_t k) {
+  return k ^ (((k >> 31) - 1u) | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over the whole workgroup of one value per thread.
+// `wsum` is kWaves words of LDS.  Contains barriers: call from all threads.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t incl = wave_inclusive_scan(v, lane);
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int j = 0; j < wid; ++j) pre += wsum[j];
+  __syncthreads();
+  return pre + incl - v;
+}
+
+// Per-tile key-value sort (paper, "Implementation", Eq. 4: the ordinal
+// transform is a key-value sort of {value, location}).  LSD radix sort with
+// 4-bit digits.  Each thread keeps `items` elements in registers; the
+// per-thread digit counts give a stable rank (thread-blocked order), a flat
+// scan over the digit-major count table gives each (digit, thread) its
+// output offset, and the elements are scattered into LDS.  Between passes
+// each thread reloads a contiguous run of `items` elements (items is odd,
+// so the strided reload hits distinct LDS banks).
+//
+// Elements: `key[i]` holds the sort key in bits [shift0, shift0 + 4*passes);
+// for float keys `pos[i]` is a 16-bit payload sorted alongside.  On entry
+// element i of thread t is element number i*kThreads + t (any order is fine
+// for the first pass); elements numbered >= T are absent.  ITEMS is odd and
+// ITEMS * kThreads >= T.
+template <int ITEMS, bool PAYLOAD>
+__device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
+                                                 int T, int shift0, int passes,
+                                                 uint32_t* kbuf, uint16_t* pbuf,
+                                                 uint16_t* cnt, uint32_t* wsum) {
+  const int t = threadIdx.x;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int sh = shift0 + 4 * pass;
+    // 1. thread-local digit counts and local ranks
+    uint64_t c_lo = 0, c_hi = 0;
+    uint32_t lr[(ITEMS + 3) / 4];
+#pragma unroll
+    for (int j = 0; j < (ITEMS + 3) / 4; ++j) lr[j] = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = pass == 0 ? i * kThreads + t : t * ITEMS + i;
+      if (e < T) {
+        const uint32_t d = (key[i] >> sh) & 15u;
+        const uint32_t s8 = (d & 7u) << 3;
+        const uint64_t sel = d < 8 ? c_lo : c_hi;
+        lr[i >> 2] |= ((uint32_t)(sel >> s8) & 0xffu) << ((i & 3) * 8);
+        const uint64_t inc = 1ull << s8;
+        if (d < 8) c_lo += inc; else c_hi += inc;
+      }
+    }
+    // 2. counts to the digit-major table
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      cnt[d * kThreads + t] = (uint16_t)((c_lo >> (8 * d)) & 0xff);
+      cnt[(d + 8) * kThreads + t] = (uint16_t)((c_hi >> (8 * d)) & 0xff);
+    }
+    __syncthreads();
+    // 3. flat exclusive scan: thread t owns table entries [16t, 16t+16)
+    {
+      uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
+      uint4 a = row[0], b = row[1];
+      uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      uint32_t run = 0, ex[16];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t lo = w[j] & 0xffffu, hi = w[j] >> 16;
+        ex[2 * j] = run;
+        run += lo;
+        ex[2 * j + 1] = run;
+        run += hi;
+      }
+      const uint32_t base = block_exclusive_scan(run, wsum);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w[j] = ((ex[2 * j] + base) & 0xffffu) | ((ex[2 * j + 1] + base) << 16);
+      row[0] = make_uint4(w[0], w[1], w[2], w[3]);
+      row[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+    __syncthreads();
+    // 4. scatter
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const int e = pass == 0 ? i * kThreads + t : t * ITEMS + i;
+      if (e < T) {
+        const uint32_t d = (key[i] >> sh) & 15u;
+        const uint32_t dst = (uint32_t)cnt[d * kThreads + t] + ((lr[i >> 2] >> ((i & 3) * 8)) & 0xffu);
+        kbuf[dst] = key[i];
+        if (PAYLOAD) pbuf[dst] = pos[i];
+      }
+    }
+    __syncthreads();
+    // 5. reload a contiguous run for the next pass
+    if (pass + 1 < passes) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const int e = t * ITEMS + i;
+        uint32_t k = 0;
+        uint16_t q = 0;
+        if (e < T) {
+          k = kbuf[e];
+          if (PAYLOAD) q = pbuf[e];
+        }
+        key[i] = k;
+        if (PAYLOAD) pos[i] = q;
+      }
+    }
+  }
+}
+
+}  // namespace mf

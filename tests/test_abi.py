@@ -1,0 +1,115 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, builds the same footprints as the oracle's rasteriser, and rejects
+bad arguments before touching the GPU.  No GPU needed."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2505_22938_amd as mf
+from oracle import footprints as OF
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not f.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([A-Za-z_]\w*)\s*\(", text, re.M):
+            name = m.group(1)
+            if name not in ("if", "while", "sizeof", "typedef"):
+                names.append(name)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mf.lib()
+    names = declared_functions()
+    assert "median_filter" in names and "mf_footprint_disc" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _set(fp):
+    return {tuple(p) for p in fp.offsets()}
+
+
+@pytest.mark.parametrize("make_lib,make_or", [
+    (lambda: mf.Footprint.disc(0), lambda: OF.disc(0)),
+    (lambda: mf.Footprint.disc(4), lambda: OF.disc(4)),
+    (lambda: mf.Footprint.disc(32), lambda: OF.disc(32)),
+    (lambda: mf.Footprint.disc(100), lambda: OF.disc(100)),
+    (lambda: mf.Footprint.disc_limit(48 * 49), lambda: OF.disc_limit(48 * 49)),
+    (lambda: mf.Footprint.ellipse(60, 20, 30), lambda: OF.ellipse(60, 20, 30)),
+    (lambda: mf.Footprint.ellipse(5, 5, 0), lambda: OF.ellipse(5, 5, 0)),
+    (lambda: mf.Footprint.regular_polygon(6, 40), lambda: OF.regular_polygon(6, 40)),
+    (lambda: mf.Footprint.regular_polygon(5, 9, 17), lambda: OF.regular_polygon(5, 9, 17)),
+    (lambda: mf.Footprint.polygon([(0, -3), (3, 2), (-3, 2)]),
+     lambda: OF.polygon([(0, -3), (3, 2), (-3, 2)])),
+])
+def test_library_footprint_equals_oracle_footprint(make_lib, make_or):
+    a = make_lib()
+    b = {tuple(int(v) for v in p) for p in make_or()}
+    assert _set(a) == b
+    assert a.taps == len(b)
+    assert a.rank == (len(b) - 1) // 2
+
+
+def test_footprint_counts_pinned():
+    assert mf.Footprint.disc(4).taps == 49
+    assert mf.Footprint.disc_limit(6).taps == 21
+    assert mf.Footprint.ellipse(60, 20, 30).taps == 3771
+    assert mf.Footprint.regular_polygon(6, 40).taps == 4145
+    f = mf.Footprint.disc(100)
+    assert (f.dx_min, f.dx_max, f.dy_min, f.dy_max) == (-100, 100, -100, 100)
+
+
+def test_footprint_errors():
+    L = mf.lib()
+    h = ctypes.c_void_p()
+    assert L.mf_footprint_disc(-1, ctypes.byref(h)) == -1
+    assert L.mf_footprint_disc(300, ctypes.byref(h)) == -3          # beyond the 255 extent
+    assert L.mf_footprint_ellipse(0.0, 1.0, 0.0, ctypes.byref(h)) == -1
+    assert L.mf_footprint_regular_polygon(2, 5.0, 0.0, ctypes.byref(h)) == -1
+    assert L.mf_status_string(-3) == b"MF_ERR_UNSUPPORTED"
+
+
+def test_argument_validation_is_host_side():
+    L = mf.lib()
+    fp = mf.Footprint.disc(2)
+    P = ctypes.c_void_p
+    # null image
+    assert L.median_filter(None, 8, 8, 8, 0, fp.handle, 0, P(4096), None) == -1
+    # stride too small / not a multiple of the element size
+    assert L.median_filter(P(4096), 8, 8, 7, 0, fp.handle, 0, P(1 << 20), None) == -1
+    assert L.median_filter(P(4096), 8, 8, 17, 1, fp.handle, 0, P(1 << 20), None) == -1
+    # bad dtype / boundary
+    assert L.median_filter(P(4096), 8, 8, 8, 7, fp.handle, 0, P(1 << 20), None) == -1
+    assert L.median_filter(P(4096), 8, 8, 8, 0, fp.handle, 5, P(1 << 20), None) == -1
+    # aliasing output
+    assert L.median_filter(P(4096), 8, 8, 8, 0, fp.handle, 0, P(4096 + 16), None) == -2
+    # empty image is a no-op
+    assert L.median_filter(P(4096), 0, 8, 8, 0, fp.handle, 0, P(1 << 20), None) == 0
+    # rank out of range
+    assert L.median_filter_rank(P(4096), 8, 8, 8, 0, fp.handle, 0, 13, P(1 << 20), None) == -1
+
+
+def test_query_plan_geometry():
+    fp = mf.Footprint.disc(32)
+    p = mf.query_plan(4096, 4096, mf.MF_U16, fp)
+    assert p["box_w"] == p["tile_w"] + 64 and p["box_h"] == p["tile_h"] + 64
+    assert p["lds_bytes"] <= 160 * 1024
+    mf.set_tile_override(32, 32)
+    try:
+        p2 = mf.query_plan(4096, 4096, mf.MF_U16, fp)
+        assert (p2["tile_w"], p2["box_w"]) == (32, 96)
+    finally:
+        mf.set_tile_override(0, 0)

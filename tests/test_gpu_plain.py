@@ -1,0 +1,153 @@
+"""GPU parity of the plain filter against the CPU oracle, bit for bit.
+
+Small cases compare every pixel.  Full-size workloads compare a seeded
+sample of pixels that the oracle computes one by one, in the same launch
+configuration the benchmark uses.
+"""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import footprints as OF
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import paper_2505_22938_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    m.lib()
+    return m
+
+
+def to_dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(mf, img, fp, boundary, **kw):
+    out = mf.median_filter(to_dev(img), fp, boundary, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint8)
+
+
+def assert_same(got, exp, what=""):
+    if not np.array_equal(bits(got), bits(exp)):
+        bad = np.argwhere(got.view(np.uint8 if got.dtype == np.uint8 else
+                                   (np.uint16 if got.dtype == np.uint16 else np.uint32)) !=
+                          exp.view(np.uint8 if exp.dtype == np.uint8 else
+                                   (np.uint16 if exp.dtype == np.uint16 else np.uint32)))
+        raise AssertionError(f"{what}: {len(bad)} mismatches, first at {bad[:5].tolist()}")
+
+
+FOOTPRINTS = {
+    "disc1": (lambda m: m.Footprint.disc(1), lambda: OF.disc(1)),
+    "disc3": (lambda m: m.Footprint.disc(3), lambda: OF.disc(3)),
+    "disc8": (lambda m: m.Footprint.disc(8), lambda: OF.disc(8)),
+    "paper_disc2": (lambda m: m.Footprint.disc_limit(6), lambda: OF.disc_limit(6)),
+    "ellipse": (lambda m: m.Footprint.ellipse(9, 3, 30), lambda: OF.ellipse(9, 3, 30)),
+    "hexagon": (lambda m: m.Footprint.regular_polygon(6, 7), lambda: OF.regular_polygon(6, 7)),
+    "triangle": (lambda m: m.Footprint.polygon([(0, -5), (6, 4), (-4, 3)]),
+                 lambda: OF.polygon([(0, -5), (6, 4), (-4, 3)])),
+}
+
+
+def make_img(dtype, w, h, seed):
+    if dtype == "f32":
+        return workloads.special_floats(w, h, seed)
+    if dtype == "u16":
+        return workloads.natural_u16(w, h, seed)
+    return workloads.uniform(w, h, dtype, seed)
+
+
+def test_plain_u8_256_disc4(mf, oracle_mod):
+    img = workloads.plain_u8(256, 256, 0)
+    fp = mf.Footprint.disc(4)
+    assert fp.taps == 49
+    assert_same(run(mf, img, fp, "clamp"), oracle_mod.filter(img, OF.disc(4), "clamp"), "c1")
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+@pytest.mark.parametrize("boundary", ["clamp", "mirror"])
+@pytest.mark.parametrize("fpname", list(FOOTPRINTS))
+def test_plain_matrix(mf, oracle_mod, dtype, boundary, fpname):
+    mk, mko = FOOTPRINTS[fpname]
+    img = make_img(dtype, 150, 77, 3)          # ragged in both directions
+    got = run(mf, img, mk(mf), boundary)
+    assert_same(got, oracle_mod.filter(img, mko(), boundary), f"{dtype}/{boundary}/{fpname}")
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 37), (41, 1), (2, 2), (3, 5), (64, 64), (65, 63)])
+@pytest.mark.parametrize("boundary", ["clamp", "mirror"])
+def test_plain_degenerate_sizes(mf, oracle_mod, w, h, boundary):
+    img = workloads.uniform(w, h, "u16", w * 100 + h)
+    for r in (0, 1, 5, 12):
+        got = run(mf, img, mf.Footprint.disc(r), boundary)
+        assert_same(got, oracle_mod.filter(img, OF.disc(r), boundary), f"{w}x{h} r={r}")
+
+
+def test_plain_padded_stride(mf, oracle_mod):
+    base = workloads.uniform(100, 50, "u8", 5)
+    dev = torch.zeros((50, 128), dtype=torch.uint8, device="cuda")
+    dev[:, :100] = to_dev(base)
+    view = dev[:, :100]
+    out = mf.median_filter(view, mf.Footprint.disc(3), "mirror")
+    torch.cuda.synchronize()
+    assert out.stride() == view.stride()
+    assert_same(out.cpu().numpy(), oracle_mod.filter(base, OF.disc(3), "mirror"), "stride")
+
+
+def test_plain_constant_and_binary(mf, oracle_mod):
+    c = np.full((70, 90), 1234, dtype=np.uint16)
+    assert_same(run(mf, c, mf.Footprint.disc(6), "clamp"), c, "constant")
+    b = workloads.binary(90, 70, 1, hi=255)
+    fp = OF.disc(5)
+    assert_same(run(mf, b, mf.Footprint.disc(5), "clamp"), oracle_mod.filter(b, fp, "clamp"),
+                "binary")
+
+
+def test_plain_rank_parameter(mf, oracle_mod):
+    img = workloads.uniform(80, 60, "u16", 9)
+    fp = OF.disc(4)
+    for k in (0, 10, 48):
+        got = run(mf, img, mf.Footprint.disc(4), "clamp", rank=k)
+        assert_same(got, oracle_mod.filter(img, fp, "clamp", rank=k), f"rank {k}")
+
+
+def test_plain_adversarial(mf, oracle_mod):
+    img = workloads.adversarial_u16(256, 256, border=40)
+    got = run(mf, img, mf.Footprint.disc(16), "clamp")
+    assert_same(got, oracle_mod.filter(img, OF.disc(16), "clamp"), "adversarial")
+
+
+@pytest.mark.parametrize("r", [16, 32, 40])
+def test_plain_large_radius_u16(mf, oracle_mod, r):
+    img = workloads.natural_u16(300, 200, seed=1)
+    got = run(mf, img, mf.Footprint.disc(r), "clamp")
+    assert_same(got, oracle_mod.filter(img, OF.disc(r), "clamp"), f"r={r}")
+
+
+def sample_points(w, h, n, seed):
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, w, n)
+    ys = rng.integers(0, h, n)
+    # always include the corners and edges
+    xs = np.concatenate([xs, [0, w - 1, 0, w - 1, w // 2, 0]])
+    ys = np.concatenate([ys, [0, 0, h - 1, h - 1, 0, h // 2]])
+    return xs, ys
+
+
+@pytest.mark.parametrize("r", [8, 32])
+def test_natural_u16_4096_sampled(mf, oracle_mod, r):
+    img = workloads.natural_u16(4096, 4096, seed=1)
+    got = run(mf, img, mf.Footprint.disc(r), "clamp")
+    xs, ys = sample_points(4096, 4096, 4000, 17)
+    exp = oracle_mod.filter_points(img, OF.disc(r), xs, ys, "clamp")
+    assert_same(got[ys, xs], exp, f"4096 r={r}")
