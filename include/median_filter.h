@@ -123,10 +123,21 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
 
 /* ------------------------------------------------------------------------
  * Tile-shape control, for measurement and tuning.  tile_w/tile_h are the
- * output tile size (multiples of 8, 8..64 wide); 0 restores the automatic
+ * output tile size: tile_w in {8, 16, 32, 64} and tile_h a multiple of
+ * 16 * (64 / tile_w) (16 waves, each owning 64/tile_w bands of equal
+ * height).  A shape whose input box exceeds 256 pixels or the LDS makes
+ * later calls return MF_ERR_UNSUPPORTED.  (0, 0) restores the automatic
  * choice.  Affects later calls from every thread.
  * ------------------------------------------------------------------------ */
 int mf_set_tile_override(int tile_w, int tile_h);
+
+/* Work counters of the plain filter, for the benchmark's work model.
+ * enable = 1: allocate (once) and zero four device counters that later
+ * calls accumulate into: [0] omnigram blocks scanned, [1] seed windows
+ * solved, [2]-[3] reserved.  enable = 0: stop counting and free them.
+ * enable = -1: copy the four counters to the host array `out4`
+ * (synchronous).  Counting adds a few scalar instructions per block. */
+int mf_work_counters(int enable, unsigned long long* out4);
 
 /* The tile shape and launch the plain filter would use for this image and
  * footprint: output tile size, input box size (tile + window extent) and

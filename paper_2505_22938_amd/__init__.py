@@ -56,6 +56,7 @@ def lib():
         "median_filter_rank": ([P, I, I, SZ, I, P, I, I, P, P], I),
         "mf_set_tile_override": ([I, I], I),
         "mf_query_plan": ([I, I, I, P, IP, IP, IP, IP, IP], I),
+        "mf_work_counters": ([I, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -201,6 +202,15 @@ def median_filter(img, fp: Footprint, boundary: str = "clamp", out=None, rank: i
 
 def set_tile_override(tile_w: int = 0, tile_h: int = 0):
     _check("mf_set_tile_override", lib().mf_set_tile_override(int(tile_w), int(tile_h)))
+
+
+def work_counters(enable: int):
+    """enable=1: start (and zero) the device work counters; 0: stop; -1: read
+    them -> [omnigram blocks scanned, seed windows solved, 0, 0]."""
+    buf = (ctypes.c_ulonglong * 4)()
+    _check("mf_work_counters", lib().mf_work_counters(int(enable),
+                                                      ctypes.cast(buf, ctypes.c_void_p)))
+    return list(buf) if enable < 0 else None
 
 
 def query_plan(w: int, h: int, dtype: int, fp: Footprint):

@@ -5,11 +5,8 @@
 //      boundary rule applied, into registers;
 //   2. ordinal transform: sort {key, location} in LDS, giving the reverse
 //      map C (sorted keys) and the omnigram (sorted locations);
-//   3. solve each output pixel's rank by scanning the omnigram in blocks of
-//      64 ordinals: one wave tests 64 omnigram entries against the window
-//      (Eq. 3 or a span lookup), ballots them into a 64-bit mask and counts
-//      it with popcount (paper, "Implementation": the 64-element bitmask and
-//      popcount refinement);
+//   3. pivot/count sliding over bands of output rows with omnigram scans
+//      (tile_engine.h);
 //   4. write C[m] for the ordinal m found.
 
 #include <hip/hip_runtime.h>
@@ -19,128 +16,14 @@
 #include <mutex>
 
 #include "mf_internal.h"
-#include "tile_common.h"
+#include "tile_engine.h"
 
 namespace mf {
 
-struct PlainArgs {
-  const void* img;
-  void* out;
-  long long stride;  // elements
-  int w, h, boundary;
-  int tw, th, tiles_x;
-  int bw, bh, T, items;
-  int dx_min, dy_min, nrows;
-  int rank;
-  int limit;                 // disc: dx^2 + dy^2 <= limit
-  const short2* spans;       // row spans, index dy - dy_min
-};
-
-template <int SHAPE>
-__device__ __forceinline__ bool member(int ox, int oy, int nrows, int dy_min, int limit,
-                                       const short2* sp) {
-  if (SHAPE == SHAPE_DISC) return ox * ox + oy * oy <= limit;
-  const int r = oy - dy_min;
-  if ((unsigned)r >= (unsigned)nrows) return false;
-  const short2 s = sp[r];
-  return ox >= s.x && ox <= s.y;
-}
-
 template <int KT, int SHAPE, int IMAX>
-__global__ __launch_bounds__(kThreads) void mf_plain_scan_kernel(PlainArgs a) {
+__global__ __launch_bounds__(kThreads) void mf_plain_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int T = a.T;
-  uint32_t* kbuf = reinterpret_cast<uint32_t*>(smem);                         // 4T
-  uint16_t* pbuf = reinterpret_cast<uint16_t*>(smem + 4 * ((T + 3) & ~3));  // 2T (f32)
-  unsigned char* after = smem + 4 * ((T + 3) & ~3) + (KT == KEY_F32 ? 2 * ((T + 7) & ~7) : 0);
-  uint16_t* cnt = reinterpret_cast<uint16_t*>(after);                        // kCounterBytes
-  uint32_t* wsum = reinterpret_cast<uint32_t*>(after + kCounterBytes);       // kWaves
-  short2* sp = reinterpret_cast<short2*>(after + kCounterBytes + 4 * kWaves);
-
-  const int t = threadIdx.x;
-  const int tile = blockIdx.x;
-  const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
-  const int gx0 = tx0 + a.dx_min, gy0 = ty0 + a.dy_min;
-
-  if (SHAPE == SHAPE_SPANS)
-    for (int i = t; i < a.nrows; i += kThreads) sp[i] = a.spans[i];
-
-  // 1. load the box, striped: element e = i*kThreads + t, row-major in the box
-  uint32_t key[IMAX];
-  uint16_t pos[IMAX];
-  {
-    int lx = t % a.bw, ly = t / a.bw;
-    const int sx = kThreads % a.bw, sy = kThreads / a.bw;
-#pragma unroll
-    for (int i = 0; i < IMAX; ++i) {
-      const int e = i * kThreads + t;
-      uint32_t k = 0, q = 0;
-      if (e < T) {
-        const int gx = remap(gx0 + lx, a.w, a.boundary);
-        const int gy = remap(gy0 + ly, a.h, a.boundary);
-        const long long off = (long long)gy * a.stride + gx;
-        const uint32_t p = (uint32_t)((ly << 8) | lx);
-        if (KT == KEY_U8) k = ((uint32_t)static_cast<const uint8_t*>(a.img)[off] << 16) | p;
-        if (KT == KEY_U16) k = ((uint32_t)static_cast<const uint16_t*>(a.img)[off] << 16) | p;
-        if (KT == KEY_F32) {
-          k = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
-          q = p;
-        }
-      }
-      key[i] = k;
-      pos[i] = (uint16_t)q;
-      lx += sx;
-      ly += sy;
-      if (lx >= a.bw) {
-        lx -= a.bw;
-        ly += 1;
-      }
-    }
-  }
-
-  // 2. ordinal transform
-  if (KT == KEY_U8)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, cnt, wsum);
-  else if (KT == KEY_U16)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, cnt, wsum);
-  else
-    block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, cnt, wsum);
-
-  // 3. rank selection by omnigram scan, one output pixel per wave at a time
-  const int lane = t & 63, wid = t >> 6;
-  const int nblk = (T + 63) >> 6;
-  const int npix = a.tw * a.th;
-  for (int p = wid; p < npix; p += kWaves) {
-    const int ox = p % a.tw, oy = p / a.tw;
-    const int gx = tx0 + ox, gy = ty0 + oy;
-    if (gx >= a.w || gy >= a.h) continue;
-    const int cx = ox - a.dx_min, cy = oy - a.dy_min;
-    int need = a.rank;
-    for (int b = 0; b < nblk; ++b) {
-      const int v = (b << 6) + lane;
-      bool in = false;
-      if (v < T) {
-        const uint32_t loc = KT == KEY_F32 ? (uint32_t)pbuf[v] : (kbuf[v] & 0xffffu);
-        in = member<SHAPE>((int)(loc & 255u) - cx, (int)(loc >> 8) - cy, a.nrows, a.dy_min,
-                           a.limit, sp);
-      }
-      const uint64_t mask = __ballot(in);
-      const int pc = __popcll(mask);
-      if (need < pc) {
-        const int below = __popcll(mask & ((1ull << lane) - 1ull));
-        const uint64_t hit = __ballot(in && below == need);
-        const int m = (b << 6) + (__ffsll((unsigned long long)hit) - 1);
-        if (lane == 0) {
-          const long long o = (long long)gy * a.stride + gx;
-          if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)(kbuf[m] >> 16);
-          if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = (uint16_t)(kbuf[m] >> 16);
-          if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m]);
-        }
-        break;
-      }
-      need -= pc;
-    }
-  }
+  tile_body<KT, SHAPE, IMAX>(a, blockIdx.x, smem);
 }
 
 // ---------------------------------------------------------------- host side
@@ -172,60 +55,95 @@ int device_info(int dev, DeviceInfo* out) {
 std::mutex g_override_mu;
 int g_tile_w = 0, g_tile_h = 0;
 
-struct Plan {
-  int tw, th, bw, bh, T, items, imax, lds;
-};
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-int lds_bytes(int T, int dtype, int nrows) {
-  const int a = 4 * ((T + 3) & ~3) + (dtype == MF_F32 ? 2 * ((T + 7) & ~7) : 0);
-  return a + kCounterBytes + 4 * kWaves + 4 * nrows;
-}
+}  // namespace
 
-int plan_for(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Plan* p) {
+// Fill the geometry and LDS layout of `d` for an output tile of tw x th.
+int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d,
+              int* imax) {
+  if (tw < 1 || tw > 64 || 64 % tw) return MF_ERR_UNSUPPORTED;
+  const int segs = 64 / tw;
+  if (th % (kWaves * segs)) return MF_ERR_UNSUPPORTED;
+  const int R = th / (kWaves * segs);
+  if (R < 1) return MF_ERR_UNSUPPORTED;
   const int ext_x = fp->dx_max - fp->dx_min, ext_y = fp->dy_max - fp->dy_min;
-  p->tw = tw;
-  p->th = th;
-  p->bw = tw + ext_x;
-  p->bh = th + ext_y;
-  if (p->bw > 256 || p->bh > 256) return MF_ERR_UNSUPPORTED;
-  p->T = p->bw * p->bh;
-  int items = (p->T + kThreads - 1) / kThreads;
-  items |= 1;
-  p->items = items;
-  p->imax = 0;
+  const int bw = tw + ext_x, bh = th + ext_y;
+  if (bw > 256 || bh > 256) return MF_ERR_UNSUPPORTED;
+  const int T = bw * bh;
+  const int need_items = ((T + kThreads - 1) / kThreads) | 1;
+  int im = 0;
   for (int c : kItemChoices)
-    if (items <= c) {
-      p->imax = c;
+    if (need_items <= c) {
+      im = c;
       break;
     }
-  if (!p->imax) return MF_ERR_UNSUPPORTED;
-  p->lds = lds_bytes(p->T, dtype, (int)fp->row_lo.size());
-  if (p->lds > lds_max) return MF_ERR_UNSUPPORTED;
+  if (!im) return MF_ERR_UNSUPPORTED;
+  // ordinal-image row pitch (16-bit elements): pitch/2 odd, so consecutive
+  // rows start in different LDS banks
+  int pitch = round_up(bw, 2);
+  if ((pitch / 2) % 2 == 0) pitch += 2;
+  const int nrows = (int)fp->row_lo.size(), ncols = (int)fp->col_lo.size();
+  const int kb = 4 * round_up(T, 4);
+  const int pb = dtype == MF_F32 ? round_up(2 * T, 16) : 0;
+  const int ib = round_up(2 * pitch * bh, 16);
+  const int hb = kWaves * 256 * 4;
+  const int B = std::max(kCounterBytes, ib + hb);
+  const int nr4 = round_up(nrows, 4);
+  const int tab = 64 + 4 * nr4 + 8 * nr4 + 16 * ncols;
+  d->tw = tw;
+  d->th = th;
+  d->bw = bw;
+  d->bh = bh;
+  d->T = T;
+  d->pitch = pitch;
+  d->segs = segs;
+  d->band_rows = R;
+  int hs = 0;
+  while (((T - 1) >> hs) >= 256) ++hs;
+  d->hist_shift = hs;
+  d->off_p = kb;
+  d->off_B = kb + pb;
+  d->off_hist = d->off_B + ib;
+  d->off_tab = d->off_B + B;
+  d->lds_bytes = d->off_tab + tab;
+  d->dx_min = fp->dx_min;
+  d->dy_min = fp->dy_min;
+  d->nrows = nrows;
+  d->ncols = ncols;
+  d->limit = (int)fp->limit;
+  *imax = im;
+  if (d->lds_bytes > lds_max) return MF_ERR_UNSUPPORTED;
   return MF_OK;
 }
 
-int choose_plan(int w, int h, int dtype, const mf_footprint* fp, int lds_max, Plan* p) {
+// Automatic tile shape: the widest band layout that fits, preferring taller
+// bands (fewer seed rows per output pixel) up to 8 rows.
+int choose_plan(int dtype, const mf_footprint* fp, int lds_max, ImageDesc* d, int* imax) {
   {
     std::lock_guard<std::mutex> lock(g_override_mu);
-    if (g_tile_w > 0) return plan_for(dtype, fp, lds_max, g_tile_w, g_tile_h, p);
+    if (g_tile_w > 0) return make_plan(dtype, fp, lds_max, g_tile_w, g_tile_h, d, imax);
   }
-  (void)w;
-  (void)h;
-  static const int sizes[] = {64, 56, 48, 40, 32, 24, 16, 8};
-  for (int s : sizes)
-    if (plan_for(dtype, fp, lds_max, s, s, p) == MF_OK) return MF_OK;
+  static const int tws[] = {64, 32, 16, 8};
+  for (int tw : tws) {
+    const int segs = 64 / tw;
+    for (int R = 8; R >= 1; R /= 2)
+      if (make_plan(dtype, fp, lds_max, tw, kWaves * segs * R, d, imax) == MF_OK) return MF_OK;
+  }
   return MF_ERR_UNSUPPORTED;
 }
 
-using KernelFn = void (*)(PlainArgs);
+namespace {
+
+using KernelFn = void (*)(ImageDesc);
 
 template <int KT, int SHAPE>
 KernelFn pick_imax(int imax) {
   switch (imax) {
-    case 9: return mf_plain_scan_kernel<KT, SHAPE, 9>;
-    case 17: return mf_plain_scan_kernel<KT, SHAPE, 17>;
-    case 25: return mf_plain_scan_kernel<KT, SHAPE, 25>;
-    default: return mf_plain_scan_kernel<KT, SHAPE, 33>;
+    case 9: return mf_plain_kernel<KT, SHAPE, 9>;
+    case 17: return mf_plain_kernel<KT, SHAPE, 17>;
+    case 25: return mf_plain_kernel<KT, SHAPE, 25>;
+    default: return mf_plain_kernel<KT, SHAPE, 33>;
   }
 }
 
@@ -237,6 +155,8 @@ KernelFn pick_kernel(int dtype, int shape, int imax) {
   return shape == SHAPE_DISC ? pick_imax<KEY_F32, SHAPE_DISC>(imax)
                              : pick_imax<KEY_F32, SHAPE_SPANS>(imax);
 }
+
+unsigned long long* g_counters = nullptr;  // device work counters, enabled on request
 
 }  // namespace
 
@@ -265,47 +185,61 @@ int launch_plain(const void* img, int w, int h, size_t stride_bytes, int dtype,
   const void* table = nullptr;
   rc = footprint_device_table(fp, dev, &table);
   if (rc) return rc;
-  Plan p;
-  rc = choose_plan(w, h, dtype, fp, di.lds_max, &p);
+  ImageDesc a{};
+  int imax = 0;
+  rc = choose_plan(dtype, fp, di.lds_max, &a, &imax);
   if (rc) return rc;
-
-  PlainArgs a;
   a.img = img;
   a.out = out;
   a.stride = (long long)(stride_bytes / (size_t)elem_size(dtype));
   a.w = w;
   a.h = h;
   a.boundary = boundary;
-  a.tw = p.tw;
-  a.th = p.th;
-  a.tiles_x = (w + p.tw - 1) / p.tw;
-  const int tiles_y = (h + p.th - 1) / p.th;
-  a.bw = p.bw;
-  a.bh = p.bh;
-  a.T = p.T;
-  a.items = p.items;
-  a.dx_min = fp->dx_min;
-  a.dy_min = fp->dy_min;
-  a.nrows = (int)fp->row_lo.size();
+  a.tiles_x = (w + a.tw - 1) / a.tw;
+  a.tiles_y = (h + a.th - 1) / a.th;
   a.rank = rank;
-  a.limit = (int)fp->limit;
   a.spans = static_cast<const short2*>(table);
+  a.counters = g_counters;
   const int shape = fp->kind == 0 ? SHAPE_DISC : SHAPE_SPANS;
-  KernelFn k = pick_kernel(dtype, shape, p.imax);
-  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds);
-  const long long ntiles = (long long)a.tiles_x * tiles_y;
+  KernelFn k = pick_kernel(dtype, shape, imax);
+  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            a.lds_bytes);
+  const long long ntiles = (long long)a.tiles_x * a.tiles_y;
   if (ntiles > 0x7fffffffLL) return MF_ERR_UNSUPPORTED;
-  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(kThreads), p.lds, stream, a);
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(kThreads), a.lds_bytes, stream, a);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   return MF_OK;
 }
 
-int query_plan(int w, int h, int dtype, const mf_footprint* fp, Plan* p) {
+int query_plan(int dtype, const mf_footprint* fp, ImageDesc* d, int* imax) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
   DeviceInfo di;
-  if (dev < 0 || device_info(dev, &di) != MF_OK) di.lds_max = 160 * 1024;
-  return choose_plan(w, h, dtype, fp, di.lds_max, p);
+  if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &di) != MF_OK) di.lds_max = 160 * 1024;
+  return choose_plan(dtype, fp, di.lds_max, d, imax);
+}
+
+int set_counters(int enable) {
+  if (enable && !g_counters) {
+    if (hipMalloc(&g_counters, 8 * sizeof(unsigned long long)) != hipSuccess) {
+      g_counters = nullptr;
+      return MF_ERR_NOMEM;
+    }
+  }
+  if (g_counters && hipMemset(g_counters, 0, 8 * sizeof(unsigned long long)) != hipSuccess)
+    return MF_ERR_HIP;
+  if (!enable && g_counters) {
+    (void)hipFree(g_counters);
+    g_counters = nullptr;
+  }
+  return MF_OK;
+}
+
+int read_counters(unsigned long long* host) {
+  if (!g_counters) return MF_ERR_INVALID_ARG;
+  if (hipMemcpy(host, g_counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return MF_ERR_HIP;
+  return MF_OK;
 }
 
 }  // namespace mf
@@ -343,7 +277,8 @@ int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
 
 int mf_set_tile_override(int tile_w, int tile_h) {
   if (tile_w < 0 || tile_h < 0 || (tile_w == 0) != (tile_h == 0)) return MF_ERR_INVALID_ARG;
-  if (tile_w && (tile_w % 8 || tile_h % 8 || tile_w > 64 || tile_h > 256))
+  if (tile_w && (tile_w > 64 || 64 % tile_w || tile_w < 8 || tile_h > 256 ||
+                 tile_h % (16 * (64 / tile_w))))
     return MF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(mf::g_override_mu);
   mf::g_tile_w = tile_w;
@@ -353,16 +288,24 @@ int mf_set_tile_override(int tile_w, int tile_h) {
 
 int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, int* tile_h,
                   int* box_w, int* box_h, int* lds) {
+  (void)w;
+  (void)h;
   if (!fp || (dtype != MF_U8 && dtype != MF_U16 && dtype != MF_F32)) return MF_ERR_INVALID_ARG;
-  mf::Plan p;
-  const int rc = mf::query_plan(w, h, dtype, fp, &p);
+  mf::ImageDesc d{};
+  int imax = 0;
+  const int rc = mf::query_plan(dtype, fp, &d, &imax);
   if (rc) return rc;
-  if (tile_w) *tile_w = p.tw;
-  if (tile_h) *tile_h = p.th;
-  if (box_w) *box_w = p.bw;
-  if (box_h) *box_h = p.bh;
-  if (lds) *lds = p.lds;
+  if (tile_w) *tile_w = d.tw;
+  if (tile_h) *tile_h = d.th;
+  if (box_w) *box_w = d.bw;
+  if (box_h) *box_h = d.bh;
+  if (lds) *lds = d.lds_bytes;
   return MF_OK;
+}
+
+int mf_work_counters(int enable, unsigned long long* out4) {
+  if (enable < 0) return out4 ? mf::read_counters(out4) : MF_ERR_INVALID_ARG;
+  return mf::set_counters(enable);
 }
 
 }  // extern "C"

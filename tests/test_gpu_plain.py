@@ -127,7 +127,7 @@ def test_plain_adversarial(mf, oracle_mod):
     assert_same(got, oracle_mod.filter(img, OF.disc(16), "clamp"), "adversarial")
 
 
-@pytest.mark.parametrize("r", [16, 32, 40])
+@pytest.mark.parametrize("r", [16, 32, 40, 48])
 def test_plain_large_radius_u16(mf, oracle_mod, r):
     img = workloads.natural_u16(300, 200, seed=1)
     got = run(mf, img, mf.Footprint.disc(r), "clamp")
