@@ -29,12 +29,13 @@ if ROOT not in sys.path:
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 
 
-def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds):
+def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
     """Algorithmic lane-operations of one filter call:
     sort 3 ops/element/4-bit pass + 1 op/element for the ordinal image,
     2*cols compare-accumulates per vertically slid pixel, 2*rows per
-    horizontally slid pixel, 64 membership tests per omnigram block scanned,
-    and one histogram update per tap of each seed window."""
+    horizontally slid pixel, 64 membership tests per wave-cooperative scan
+    block, 4 per group tested by one lane, and one histogram update per tap
+    of each seed window."""
     tw, th = plan["tile_w"], plan["tile_h"]
     T = plan["box_w"] * plan["box_h"]
     tiles = -(-w // tw) * -(-h // th)
@@ -42,11 +43,12 @@ def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds):
     seed_rows = seeds * tw                     # first rows of bands
     sort_ops = tiles * T * (3 * passes + 1)
     slide_ops = (npx - seed_rows) * 2 * cols + (seed_rows - seeds) * 2 * rows
-    scan_ops = 64 * blocks
+    scan_ops = 64 * blocks + 4 * groups
     seed_ops = seeds * taps
     total = sort_ops + slide_ops + scan_ops + seed_ops
     return dict(total=total, sort=sort_ops, slide=slide_ops, scan=scan_ops, seed=seed_ops,
-                blocks_per_px=blocks / npx, tiles=tiles, computed_px=npx)
+                blocks_per_px=blocks / npx, groups_per_px=groups / npx, tiles=tiles,
+                computed_px=npx)
 
 
 def main():
@@ -104,18 +106,21 @@ def main():
     mf.work_counters(1)
     mf.median_filter(img, fp, "clamp", out=out)
     torch.cuda.synchronize()
-    blocks, seeds, _, _ = mf.work_counters(-1)
+    cnt = mf.work_counters(-1)
+    blocks, seeds, groups = cnt[0], cnt[1], cnt[6]
+    nw = max(cnt[5], 1)
+    phase_clk = {"sort": cnt[2] / nw, "rows": cnt[3] / nw, "sweep": cnt[4] / nw}
     mf.work_counters(0)
     lo, hi = fp.row_spans()
     rows = len(lo)
     cols = fp.dx_max - fp.dx_min + 1
-    wm = work_model(plan, fp.taps, rows, cols, S, S, 4, blocks, seeds)
+    wm = work_model(plan, fp.taps, rows, cols, S, S, 4, blocks, seeds, groups)
     kmean = float(np.mean(kern_ms))
     achieved = wm["total"] / (kmean * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Top/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
                 "traffic": None, "kernel_ms_mean": kmean, "kernel_ms_min": float(np.min(kern_ms)),
-                "work_lane_ops": wm}
+                "work_lane_ops": wm, "clocks_per_wave": phase_clk}
     gpu_out = out.cpu().numpy()
 
     cpu = None

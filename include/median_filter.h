@@ -132,12 +132,15 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
 int mf_set_tile_override(int tile_w, int tile_h);
 
 /* Work counters of the plain filter, for the benchmark's work model.
- * enable = 1: allocate (once) and zero four device counters that later
- * calls accumulate into: [0] omnigram blocks scanned, [1] seed windows
- * solved, [2]-[3] reserved.  enable = 0: stop counting and free them.
- * enable = -1: copy the four counters to the host array `out4`
- * (synchronous).  Counting adds a few scalar instructions per block. */
-int mf_work_counters(int enable, unsigned long long* out4);
+ * enable = 1: allocate (once) and zero eight device counters that later
+ * calls accumulate into: [0] wave-cooperative omnigram blocks scanned
+ * (64 ordinals each), [1] seed windows solved, [2] [3] [4] shader clocks summed over waves spent in load+sort,
+ * in seeds and first band rows, and in vertical sweeps, [5] number of
+ * waves summed, [6] lane-parallel 4-ordinal groups tested, [7] reserved.  enable = 0: stop counting and free
+ * them.  enable = -1: copy the eight counters to the host array `out8`
+ * (synchronous).  Not thread-safe against concurrent filter calls.
+ * Counting adds a few scalar instructions per block. */
+int mf_work_counters(int enable, unsigned long long* out8);
 
 /* The tile shape and launch the plain filter would use for this image and
  * footprint: output tile size, input box size (tile + window extent) and

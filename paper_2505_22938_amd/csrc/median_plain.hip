@@ -220,12 +220,12 @@ int query_plan(int dtype, const mf_footprint* fp, ImageDesc* d, int* imax) {
 
 int set_counters(int enable) {
   if (enable && !g_counters) {
-    if (hipMalloc(&g_counters, 8 * sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc(&g_counters, CNT_SLOTS * sizeof(unsigned long long)) != hipSuccess) {
       g_counters = nullptr;
       return MF_ERR_NOMEM;
     }
   }
-  if (g_counters && hipMemset(g_counters, 0, 8 * sizeof(unsigned long long)) != hipSuccess)
+  if (g_counters && hipMemset(g_counters, 0, CNT_SLOTS * sizeof(unsigned long long)) != hipSuccess)
     return MF_ERR_HIP;
   if (!enable && g_counters) {
     (void)hipFree(g_counters);
@@ -236,8 +236,8 @@ int set_counters(int enable) {
 
 int read_counters(unsigned long long* host) {
   if (!g_counters) return MF_ERR_INVALID_ARG;
-  if (hipMemcpy(host, g_counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
-      hipSuccess)
+  if (hipMemcpy(host, g_counters, CNT_SLOTS * sizeof(unsigned long long),
+                hipMemcpyDeviceToHost) != hipSuccess)
     return MF_ERR_HIP;
   return MF_OK;
 }
@@ -303,8 +303,8 @@ int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, 
   return MF_OK;
 }
 
-int mf_work_counters(int enable, unsigned long long* out4) {
-  if (enable < 0) return out4 ? mf::read_counters(out4) : MF_ERR_INVALID_ARG;
+int mf_work_counters(int enable, unsigned long long* out8) {
+  if (enable < 0) return out8 ? mf::read_counters(out8) : MF_ERR_INVALID_ARG;
   return mf::set_counters(enable);
 }
 

@@ -50,7 +50,19 @@ struct ImageDesc {
   unsigned long long* counters;  // optional work counters (null: off)
 };
 
-enum { CNT_BLOCKS = 0, CNT_SEEDS = 1, CNT_PIXELS = 2, CNT_SEED_TAPS = 3 };
+// Work counters (accumulated only when ImageDesc::counters is set).
+constexpr int kLaneBudget = 64;  // 4-ordinal groups a lane tests before the wave helps
+
+enum {
+  CNT_BLOCKS = 0,      // wave-cooperative omnigram blocks scanned (64 ordinals each)
+  CNT_SEEDS = 1,       // seed windows solved from a histogram
+  CNT_CYC_SORT = 2,    // shader clocks per wave: load + sort + ordinal image
+  CNT_CYC_ROW = 3,     // shader clocks per wave: seeds + first rows of bands
+  CNT_CYC_SWEEP = 4,   // shader clocks per wave: vertical sweeps
+  CNT_WAVES = 5,       // waves that reported clocks
+  CNT_GROUPS = 6,      // lane-parallel 4-ordinal groups tested (summed over lanes)
+  CNT_SLOTS = 8
+};
 
 // Set lane L of a per-lane value to a wave-uniform value.
 __device__ __forceinline__ int set_lane(int v, int L, int old) {
@@ -68,15 +80,49 @@ __device__ __forceinline__ uint32_t omega_at(const uint32_t* kbuf, const uint16_
   return KT == KEY_F32 ? (uint32_t)pbuf[v] : (kbuf[v] & 0xffffu);
 }
 
+typedef short s2v __attribute__((ext_vector_type(2)));
+
+// Window membership of an omnigram entry (paper, Eq. 2/3).  `w` holds the
+// entry's box location in its low 16 bits (x: bits 0-7, y: bits 8-15);
+// `cxy` is the window centre packed as x | y << 16.  The offset is formed
+// with one byte permute and one packed 16-bit subtract; a disc then needs one
+// 16-bit dot product, other shapes one span lookup by row.
+template <int SHAPE>
+__device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limit, int dy_min,
+                                              int nrows, const short2* rsp) {
+  const uint32_t pk = __builtin_amdgcn_perm(0u, w, 0x0c010c00u);
+  const s2v d = __builtin_bit_cast(s2v, pk) - __builtin_bit_cast(s2v, cxy);
+  if (SHAPE == SHAPE_DISC) return __builtin_amdgcn_sdot2(d, d, 0, false) <= limit;
+  const int r = (int)d.y - dy_min;
+  if ((unsigned)r >= (unsigned)nrows) return false;
+  const short2 s = rsp[r];
+  return (int)d.x >= (int)s.x && (int)d.x <= (int)s.y;
+}
+
 template <int SHAPE>
 __device__ __forceinline__ bool in_window(uint32_t loc, int cx, int cy, int limit, int dy_min,
                                           int nrows, const short2* rsp) {
-  const int ox = (int)(loc & 255u) - cx, oy = (int)(loc >> 8) - cy;
-  if (SHAPE == SHAPE_DISC) return ox * ox + oy * oy <= limit;
-  const int r = oy - dy_min;
-  if ((unsigned)r >= (unsigned)nrows) return false;
-  const short2 s = rsp[r];
-  return ox >= s.x && ox <= s.y;
+  return member_packed<SHAPE>(loc, (uint32_t)cx | ((uint32_t)cy << 16), limit, dy_min, nrows,
+                              rsp);
+}
+
+// Load the four omnigram entries of aligned group q (q % 4 == 0).
+template <int KT>
+__device__ __forceinline__ void load_group(const uint32_t* kbuf, const uint16_t* pbuf, int q,
+                                           uint32_t (&e)[4]) {
+  if (KT == KEY_F32) {
+    const uint2 g = *reinterpret_cast<const uint2*>(pbuf + q);
+    e[0] = g.x;
+    e[1] = g.x >> 16;
+    e[2] = g.y;
+    e[3] = g.y >> 16;
+  } else {
+    const uint4 g = *reinterpret_cast<const uint4*>(kbuf + q);
+    e[0] = g.x;
+    e[1] = g.y;
+    e[2] = g.z;
+    e[3] = g.w;
+  }
 }
 
 // Rank selection for one window (wave-uniform arguments): given a pivot
@@ -134,6 +180,71 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
     }
   }
   return -1;  // unreachable for a consistent omnigram
+}
+
+// Lane-parallel rank selection: every lane refines its own window.  Same
+// contract as scan_select, per lane: pivot p with c window members below it.
+// The lane walks the omnigram from p upwards (c <= k) or downwards, four
+// ordinals per LDS read (one aligned 16-byte group of W, or 8 bytes of the
+// location array for float keys), counting members until the one of rank k
+// is reached.  Used where windows move little between steps (vertical
+// slides), so each lane walks a short distance.
+template <int KT, int SHAPE>
+__device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget,
+                                           const ImageDesc& a, const uint32_t* kbuf,
+                                           const uint16_t* pbuf, const short2* rsp, int& groups) {
+  const bool up = c <= k;
+  int need = up ? k - c : c - 1 - k;
+  const int lo = up ? p : 0;
+  const unsigned span = (unsigned)(up ? a.T - p : p);
+  int q = up ? (p & ~3) : ((p - 1) & ~3);
+  int below = c;                 // members below the scanned frontier
+  int m = -1;
+  int it = 0;
+  while (q >= 0 && q < a.T && it < budget) {
+    ++it;
+    uint32_t e[4];
+    load_group<KT>(kbuf, pbuf, q, e);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool ok = (unsigned)(q + j - lo) < span &&
+                      member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp);
+      bits |= (uint32_t)ok << j;
+    }
+    const int cnt = __builtin_popcount(bits);
+    if (need < cnt) {
+      int n = need, jsel = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int jj = up ? t : 3 - t;
+        if ((bits >> jj) & 1u) {
+          if (n == 0) jsel = jj;
+          --n;
+        }
+      }
+      m = q + jsel;
+      break;
+    }
+    need -= cnt;
+    if (up) {
+      below += cnt;
+      q += 4;
+    } else {
+      below -= cnt;
+      q -= 4;
+    }
+  }
+  groups += it;
+  if (m < 0) {
+    // frontier for a wave-cooperative finish: ordinals scanned so far lie
+    // in [p, q) (up) or [q + 4, p) (down)
+    p = up ? q : q + 4;
+    if (p < 0) p = 0;
+    if (p > a.T) p = a.T;
+    c = below;
+  }
+  return m;
 }
 
 // Seed solve for the window centred at box (cx, cy): histogram of its
@@ -227,6 +338,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
+  const long long clk0 = a.counters ? (long long)clock64() : 0;
   const int gx0 = tx0 + a.dx_min, gy0 = ty0 + a.dy_min;
 
   // footprint tables: row spans, per-row horizontal offsets, per-column
@@ -291,11 +403,12 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
   }
   __syncthreads();
+  const long long clk1 = a.counters ? (long long)clock64() : 0;
 
   // 4. bands
   const int k = a.rank;
   uint32_t* hist = hist_all + wid * 256;
-  int blocks = 0, seeds = 0, seed_taps = 0;
+  int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;
   const int seg = lane / tw, col = lane - seg * tw;
   const int band = wid * segs + seg;
@@ -317,6 +430,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     }
   }
   if (a.counters) seed_taps = seeds;  // taps per seed added on the host
+  const long long clk2 = a.counters ? (long long)clock64() : 0;
   {
     const int gx = tx0 + col, gy = ty0 + row0;
     if (lane < segs * tw && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, m);
@@ -334,15 +448,19 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
         delta += (int)(I[lbase + o.x] < m) - (int)(I[lbase + o.y] < m);
       }
     }
-    const int cnew = k + delta;
+    int pl = m, cl = k + delta;
     int mnew = m;
-    for (int L = 0; L < segs * tw; ++L) {
-      const int pL = __builtin_amdgcn_readlane(m, L);
-      const int cL = __builtin_amdgcn_readlane(cnew, L);
-      const int sL = L / tw;
-      const int cxL = (L - sL * tw) - a.dx_min;
-      const int cyL = (wid * segs + sL) * R + r - a.dy_min;
-      const int mL = scan_select<KT, SHAPE>(pL, cL, k, cxL, cyL, a, kbuf, pbuf, rsp, blocks);
+    const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
+    if (lane_active)
+      mnew = lane_select<KT, SHAPE>(pl, cl, k, cxy, kLaneBudget, a, kbuf, pbuf, rsp, groups);
+    uint64_t left = __ballot(lane_active && mnew < 0);
+    while (left) {
+      const int L = __ffsll((unsigned long long)left) - 1;
+      left &= left - 1;
+      const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
+      const int mL = scan_select<KT, SHAPE>(__builtin_amdgcn_readlane(pl, L),
+                                            __builtin_amdgcn_readlane(cl, L), k, cxyL & 0xffff,
+                                            cxyL >> 16, a, kbuf, pbuf, rsp, blocks);
       mnew = set_lane(mL, L, mnew);
     }
     m = mnew;
@@ -351,8 +469,19 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   }
 
   if (a.counters && lane == 0) {
+    const long long clk3 = (long long)clock64();
     atomicAdd(&a.counters[CNT_BLOCKS], (unsigned long long)blocks);
     atomicAdd(&a.counters[CNT_SEEDS], (unsigned long long)seed_taps);
+    atomicAdd(&a.counters[CNT_CYC_SORT], (unsigned long long)(clk1 - clk0));
+    atomicAdd(&a.counters[CNT_CYC_ROW], (unsigned long long)(clk2 - clk1));
+    atomicAdd(&a.counters[CNT_CYC_SWEEP], (unsigned long long)(clk3 - clk2));
+    atomicAdd(&a.counters[CNT_WAVES], 1ull);
+  }
+  if (a.counters) {
+    // lane-parallel groups differ per lane: sum over the wave
+    unsigned long long gsum = (unsigned long long)groups;
+    for (int d = 32; d >= 1; d >>= 1) gsum += __shfl_xor(gsum, d, 64);
+    if (lane == 0) atomicAdd(&a.counters[CNT_GROUPS], gsum);
   }
 }
 
