@@ -34,7 +34,7 @@ def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
     sort 3 ops/element/4-bit pass + 1 op/element for the ordinal image,
     2*cols compare-accumulates per vertically slid pixel, 2*rows per
     horizontally slid pixel, 64 membership tests per wave-cooperative scan
-    block, 4 per group tested by one lane, and one histogram update per tap
+    block, 8 per group tested by one lane, and one histogram update per tap
     of each seed window."""
     tw, th = plan["tile_w"], plan["tile_h"]
     T = plan["box_w"] * plan["box_h"]
@@ -43,7 +43,7 @@ def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
     seed_rows = seeds * tw                     # first rows of bands
     sort_ops = tiles * T * (3 * passes + 1)
     slide_ops = (npx - seed_rows) * 2 * cols + (seed_rows - seeds) * 2 * rows
-    scan_ops = 64 * blocks + 4 * groups
+    scan_ops = 64 * blocks + 8 * groups
     seed_ops = seeds * taps
     total = sort_ops + slide_ops + scan_ops + seed_ops
     return dict(total=total, sort=sort_ops, slide=slide_ops, scan=scan_ops, seed=seed_ops,

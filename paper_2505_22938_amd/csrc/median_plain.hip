@@ -69,7 +69,7 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   if (R < 1) return MF_ERR_UNSUPPORTED;
   const int ext_x = fp->dx_max - fp->dx_min, ext_y = fp->dy_max - fp->dy_min;
   const int bw = tw + ext_x, bh = th + ext_y;
-  if (bw > 256 || bh > 256) return MF_ERR_UNSUPPORTED;
+  if (bw > 255 || bh > 256) return MF_ERR_UNSUPPORTED;   // (255, 255) must lie outside the box
   const int T = bw * bh;
   const int need_items = ((T + kThreads - 1) / kThreads) | 1;
   int im = 0;
@@ -84,10 +84,16 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   int pitch = round_up(bw, 2);
   if ((pitch / 2) % 2 == 0) pitch += 2;
   const int nrows = (int)fp->row_lo.size(), ncols = (int)fp->col_lo.size();
-  const int kb = 4 * round_up(T, 4);
-  const int pb = dtype == MF_F32 ? round_up(2 * T, 16) : 0;
+  // region A: sort exchange (4T); afterwards the omnigram (2T) and the
+  // reverse map (2T) for 8/16-bit keys, or keys (4T) + locations (2T) for
+  // float keys.  Region B: digit counts during the sort, then the ordinal
+  // image and the per-wave seed histograms.
+  // omega and C each hold T entries plus 16 padding entries, 16-byte aligned
+  const int TP = round_up(T, 8) + 16;
+  const int kb = dtype == MF_F32 ? 4 * round_up(T, 4) : 4 * TP;
+  const int pb = dtype == MF_F32 ? 2 * TP : 0;
   const int ib = round_up(2 * pitch * bh, 16);
-  const int hb = kWaves * 256 * 4;
+  const int hb = kWaves * 128 * 4;
   const int B = std::max(kCounterBytes, ib + hb);
   const int nr4 = round_up(nrows, 4);
   const int tab = 64 + 4 * nr4 + 8 * nr4 + 16 * ncols;
@@ -103,6 +109,7 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   while (((T - 1) >> hs) >= 256) ++hs;
   d->hist_shift = hs;
   d->off_p = kb;
+  d->off_C = 2 * TP;
   d->off_B = kb + pb;
   d->off_hist = d->off_B + ib;
   d->off_tab = d->off_B + B;

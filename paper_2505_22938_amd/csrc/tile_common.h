@@ -74,10 +74,15 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // element i of thread t is element number i*kThreads + t (any order is fine
 // for the first pass); elements numbered >= T are absent.  ITEMS is odd and
 // ITEMS * kThreads >= T.
+//
+// Output: with PAYLOAD (float keys) the sorted keys go to kbuf and the
+// payload to pbuf.  Without PAYLOAD the element is one word key << 16 | loc;
+// the last pass splits it into loc -> omega[dst] and key -> crev[dst].
 template <int ITEMS, bool PAYLOAD>
 __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
                                                  int T, int shift0, int passes,
                                                  uint32_t* kbuf, uint16_t* pbuf,
+                                                 uint16_t* omega, uint16_t* crev,
                                                  uint16_t* cnt, uint32_t* wsum) {
   const int t = threadIdx.x;
   for (int pass = 0; pass < passes; ++pass) {
@@ -134,8 +139,15 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
       if (e < T) {
         const uint32_t d = (key[i] >> sh) & 15u;
         const uint32_t dst = (uint32_t)cnt[d * kThreads + t] + ((lr[i >> 2] >> ((i & 3) * 8)) & 0xffu);
-        kbuf[dst] = key[i];
-        if (PAYLOAD) pbuf[dst] = pos[i];
+        if (PAYLOAD) {
+          kbuf[dst] = key[i];
+          pbuf[dst] = pos[i];
+        } else if (pass + 1 < passes) {
+          kbuf[dst] = key[i];
+        } else {
+          omega[dst] = (uint16_t)key[i];
+          crev[dst] = (uint16_t)(key[i] >> 16);
+        }
       }
     }
     __syncthreads();

@@ -46,12 +46,12 @@ struct ImageDesc {
   int segs, band_rows, hist_shift;
   const short2* spans;  // nrows row spans (index dy - dy_min) then ncols column spans
   // LDS layout, bytes
-  int off_p, off_B, off_hist, off_tab, lds_bytes;
+  int off_p, off_C, off_B, off_hist, off_tab, lds_bytes;
   unsigned long long* counters;  // optional work counters (null: off)
 };
 
 // Work counters (accumulated only when ImageDesc::counters is set).
-constexpr int kLaneBudget = 64;  // 4-ordinal groups a lane tests before the wave helps
+constexpr int kLaneBudget = 32;  // 8-ordinal groups a lane tests before the wave helps
 
 enum {
   CNT_BLOCKS = 0,      // wave-cooperative omnigram blocks scanned (64 ordinals each)
@@ -60,7 +60,7 @@ enum {
   CNT_CYC_ROW = 3,     // shader clocks per wave: seeds + first rows of bands
   CNT_CYC_SWEEP = 4,   // shader clocks per wave: vertical sweeps
   CNT_WAVES = 5,       // waves that reported clocks
-  CNT_GROUPS = 6,      // lane-parallel 4-ordinal groups tested (summed over lanes)
+  CNT_GROUPS = 6,      // lane-parallel 8-ordinal groups tested (summed over lanes)
   CNT_SLOTS = 8
 };
 
@@ -75,10 +75,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int KT>
-__device__ __forceinline__ uint32_t omega_at(const uint32_t* kbuf, const uint16_t* pbuf, int v) {
-  return KT == KEY_F32 ? (uint32_t)pbuf[v] : (kbuf[v] & 0xffffu);
-}
 
 typedef short s2v __attribute__((ext_vector_type(2)));
 
@@ -99,53 +95,31 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
   return (int)d.x >= (int)s.x && (int)d.x <= (int)s.y;
 }
 
-template <int SHAPE>
-__device__ __forceinline__ bool in_window(uint32_t loc, int cx, int cy, int limit, int dy_min,
-                                          int nrows, const short2* rsp) {
-  return member_packed<SHAPE>(loc, (uint32_t)cx | ((uint32_t)cy << 16), limit, dy_min, nrows,
-                              rsp);
-}
-
-// Load the four omnigram entries of aligned group q (q % 4 == 0).
-template <int KT>
-__device__ __forceinline__ void load_group(const uint32_t* kbuf, const uint16_t* pbuf, int q,
-                                           uint32_t (&e)[4]) {
-  if (KT == KEY_F32) {
-    const uint2 g = *reinterpret_cast<const uint2*>(pbuf + q);
-    e[0] = g.x;
-    e[1] = g.x >> 16;
-    e[2] = g.y;
-    e[3] = g.y >> 16;
-  } else {
-    const uint4 g = *reinterpret_cast<const uint4*>(kbuf + q);
-    e[0] = g.x;
-    e[1] = g.y;
-    e[2] = g.z;
-    e[3] = g.w;
-  }
-}
 
 // Rank selection for one window (wave-uniform arguments): given a pivot
 // ordinal p and the number c of window members with ordinal < p, return the
 // member ordinal m with exactly k members below it.  The omnigram is tested
 // 64 ordinals per step, one per lane (Eq. 2/3), and the block's members
-// counted with one ballot and popcount (paper, "Implementation").
-template <int KT, int SHAPE>
-__device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
-                                           const ImageDesc& a, const uint32_t* kbuf,
-                                           const uint16_t* pbuf, const short2* rsp,
-                                           int& blocks) {
+// counted with one ballot and popcount (paper, "Implementation").  The next
+// block is loaded while the current one is tested.  pre_up / pre_dn are
+// this lane's entries of the first block above p ([p, p+64)) and below p
+// ([p-64, p)), loaded by the caller (only the one for the taken direction
+// is used).
+template <int SHAPE>
+__device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, const ImageDesc& a,
+                                         const uint16_t* om, const short2* rsp, int& blocks,
+                                         uint32_t pre_up, uint32_t pre_dn) {
   const int lane = threadIdx.x & 63;
   const int T = a.T;
   const int cap = (T >> 6) + 2;
   if (c <= k) {
     int need = k - c;
     int b = p;
+    uint32_t cur = pre_up;
     for (int it = 0; it < cap; ++it, b += 64) {
-      const int v = b + lane;
-      bool in = false;
-      if (v < T) in = in_window<SHAPE>(omega_at<KT>(kbuf, pbuf, v), cx, cy, a.limit, a.dy_min,
-                                       a.nrows, rsp);
+      const uint32_t nxt = om[min(b + 64 + lane, T - 1)];
+      const bool in = b + lane < T &&
+                      member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
       const uint64_t mask = __ballot(in);
       const int pc = __popcll(mask);
       ++blocks;
@@ -156,16 +130,17 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
         return b + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
+      cur = nxt;
     }
   } else {
     int need = c - k;
     int b = p;
+    uint32_t cur = pre_dn;
     for (int it = 0; it < cap; ++it, b -= 64) {
+      const uint32_t nxt = om[max(b - 128 + lane, 0)];
       const int v = b - 64 + lane;
-      bool in = false;
-      if (v >= 0 && v < T)
-        in = in_window<SHAPE>(omega_at<KT>(kbuf, pbuf, v), cx, cy, a.limit, a.dy_min, a.nrows,
-                              rsp);
+      const bool in = v >= 0 && v < T &&
+                      member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
       const uint64_t mask = __ballot(in);
       const int pc = __popcll(mask);
       ++blocks;
@@ -177,47 +152,90 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
         return b - 64 + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
+      cur = nxt;
     }
   }
   return -1;  // unreachable for a consistent omnigram
 }
 
+template <int KT, int SHAPE>
+__device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
+                                           const ImageDesc& a, const uint16_t* om,
+                                           const short2* rsp, int& blocks) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
+  const bool up = c <= k;
+  const uint32_t pre = up ? om[min(p + lane, a.T - 1)] : om[max(p - 64 + lane, 0)];
+  return scan_core<SHAPE>(p, c, k, cxy, a, om, rsp, blocks, pre, pre);
+}
+
 // Lane-parallel rank selection: every lane refines its own window.  Same
 // contract as scan_select, per lane: pivot p with c window members below it.
-// The lane walks the omnigram from p upwards (c <= k) or downwards, four
-// ordinals per LDS read (one aligned 16-byte group of W, or 8 bytes of the
-// location array for float keys), counting members until the one of rank k
-// is reached.  Used where windows move little between steps (vertical
-// slides), so each lane walks a short distance.
-template <int KT, int SHAPE>
+// The lane walks the omnigram from p upwards (c <= k) or downwards, eight
+// ordinals per 16-byte LDS read, counting members until the one of rank k is
+// reached.  Used where windows move little between steps (vertical slides),
+// so each lane walks a short distance.  The omnigram is padded past T with
+// entries located outside the box, so only the first group needs a range
+// test.  After `budget` groups an unfinished lane returns -1 with (p, c) set
+// to its frontier, for a wave-cooperative finish.
+template <int SHAPE>
 __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget,
-                                           const ImageDesc& a, const uint32_t* kbuf,
-                                           const uint16_t* pbuf, const short2* rsp, int& groups) {
+                                           const ImageDesc& a, const uint16_t* om,
+                                           const short2* rsp, int& groups) {
   const bool up = c <= k;
   int need = up ? k - c : c - 1 - k;
-  const int lo = up ? p : 0;
-  const unsigned span = (unsigned)(up ? a.T - p : p);
-  int q = up ? (p & ~3) : ((p - 1) & ~3);
-  int below = c;                 // members below the scanned frontier
-  int m = -1;
-  int it = 0;
-  while (q >= 0 && q < a.T && it < budget) {
-    ++it;
-    uint32_t e[4];
-    load_group<KT>(kbuf, pbuf, q, e);
+  int q = up ? (p & ~7) : ((p - 1) & ~7);
+  int below = c;   // members below the frontier
+  int m = -1, it = 0;
+  // first (partial) group: only ordinals in [p, T) (up) or [0, p) (down);
+  // p > 0 whenever the walk goes down, so q >= 0
+  {
+    const uint4 g = *reinterpret_cast<const uint4*>(om + max(q, 0));
+    const uint32_t e[8] = {g.x, g.x >> 16, g.y, g.y >> 16, g.z, g.z >> 16, g.w, g.w >> 16};
     uint32_t bits = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool ok = (unsigned)(q + j - lo) < span &&
-                      member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp);
-      bits |= (uint32_t)ok << j;
+    for (int j = 0; j < 8; ++j) {
+      const bool in_range = up ? (q + j >= p) : (q + j < p);
+      bits |= (uint32_t)(in_range &&
+                         member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp)) << j;
     }
     const int cnt = __builtin_popcount(bits);
+    ++it;
     if (need < cnt) {
       int n = need, jsel = 0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int jj = up ? t : 3 - t;
+      for (int t = 0; t < 8; ++t) {
+        const int jj = up ? t : 7 - t;
+        if ((bits >> jj) & 1u) {
+          if (n == 0) jsel = jj;
+          --n;
+        }
+      }
+      m = q + jsel;
+    } else {
+      need -= cnt;
+      below += up ? cnt : -cnt;
+      q += up ? 8 : -8;
+    }
+  }
+  // full groups: count members only
+  while (m < 0 && (up ? q < a.T : q >= 0) && it < budget) {
+    const uint4 g = *reinterpret_cast<const uint4*>(om + q);
+    const uint32_t e[8] = {g.x, g.x >> 16, g.y, g.y >> 16, g.z, g.z >> 16, g.w, g.w >> 16};
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      cnt += (int)member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp);
+    ++it;
+    if (need < cnt) {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        bits |= (uint32_t)member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp) << j;
+      int n = need, jsel = 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int jj = up ? t : 7 - t;
         if ((bits >> jj) & 1u) {
           if (n == 0) jsel = jj;
           --n;
@@ -227,19 +245,12 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
       break;
     }
     need -= cnt;
-    if (up) {
-      below += cnt;
-      q += 4;
-    } else {
-      below -= cnt;
-      q -= 4;
-    }
+    below += up ? cnt : -cnt;
+    q += up ? 8 : -8;
   }
   groups += it;
   if (m < 0) {
-    // frontier for a wave-cooperative finish: ordinals scanned so far lie
-    // in [p, q) (up) or [q + 4, p) (down)
-    p = up ? q : q + 4;
+    p = up ? q : q + 8;
     if (p < 0) p = 0;
     if (p > a.T) p = a.T;
     c = below;
@@ -251,26 +262,26 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 // ordinals >> hist_shift, pick the bin holding rank k, refine by scanning.
 template <int KT, int SHAPE>
 __device__ __forceinline__ int seed_solve(int cx, int cy, const ImageDesc& a,
-                                          const uint32_t* kbuf, const uint16_t* pbuf,
-                                          const uint16_t* I, uint32_t* hist, const short2* rsp,
-                                          int& blocks) {
+                                          const uint16_t* om, const uint16_t* I, uint32_t* hist,
+                                          const short2* rsp, int& blocks) {
   const int lane = threadIdx.x & 63;
   const int k = a.rank;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) hist[lane * 4 + j] = 0;
+  // 256 bins of 16-bit counts, two per word (a window has < 65536 taps)
+  hist[lane * 2] = 0;
+  hist[lane * 2 + 1] = 0;
   wave_lds_sync();
   for (int i = lane; i < a.nrows; i += 64) {
     const short2 s = rsp[i];
     const int row = (cy + a.dy_min + i) * a.pitch + cx;
-    for (int x = s.x; x <= s.y; ++x) atomicAdd(&hist[I[row + x] >> a.hist_shift], 1u);
+    for (int x = s.x; x <= s.y; ++x) {
+      const uint32_t b = (uint32_t)I[row + x] >> a.hist_shift;
+      atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
+    }
   }
   wave_lds_sync();
-  uint32_t h[4], sum = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    h[j] = hist[lane * 4 + j];
-    sum += h[j];
-  }
+  const uint32_t w0 = hist[lane * 2], w1 = hist[lane * 2 + 1];
+  uint32_t h[4] = {w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16};
+  const uint32_t sum = h[0] + h[1] + h[2] + h[3];
   uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
   int bin = -1;
   uint32_t base = 0;
@@ -286,37 +297,44 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, const ImageDesc& a,
   const int src = __ffsll((unsigned long long)who) - 1;
   const int sbin = __builtin_amdgcn_readlane(bin, src);
   const int sbase = __builtin_amdgcn_readlane((int)base, src);
-  return scan_select<KT, SHAPE>(sbin << a.hist_shift, sbase, k, cx, cy, a, kbuf, pbuf, rsp,
-                                blocks);
+  return scan_select<KT, SHAPE>(sbin << a.hist_shift, sbase, k, cx, cy, a, om, rsp, blocks);
 }
 
 // Count change when the window centred at box (cx, cy) moves right by one
-// pixel, against pivot p: one footprint row per lane (rows beyond 64 in
-// further passes); hrow[i] = (entering offset, leaving offset) of row i.
+// pixel, against pivot p: lanes take footprint rows lane and lane + 64 (and
+// further rounds of 128 rows for taller windows); hrow[i] = (entering
+// offset, leaving offset) of row i.
 __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDesc& a,
                                            const uint16_t* I, const int2* hrow) {
   const int lane = threadIdx.x & 63;
   const int base = cy * a.pitch + cx;
   int delta = 0;
-  for (int i0 = 0; i0 < a.nrows; i0 += 64) {
-    const int i = i0 + lane;
-    bool e = false, l = false;
-    if (i < a.nrows) {
-      const int2 o = hrow[i];
-      e = I[base + o.x] < p;
-      l = I[base + o.y] < p;
+  for (int i0 = 0; i0 < a.nrows; i0 += 128) {
+    const int i1 = i0 + lane, i2 = i0 + 64 + lane;
+    bool e1 = false, l1 = false, e2 = false, l2 = false;
+    if (i1 < a.nrows) {
+      const int2 o = hrow[i1];
+      e1 = I[base + o.x] < p;
+      l1 = I[base + o.y] < p;
     }
-    delta += __popcll(__ballot(e)) - __popcll(__ballot(l));
+    if (i2 < a.nrows) {
+      const int2 o = hrow[i2];
+      e2 = I[base + o.x] < p;
+      l2 = I[base + o.y] < p;
+    }
+    delta += __popcll(__ballot(e1)) + __popcll(__ballot(e2)) - __popcll(__ballot(l1)) -
+             __popcll(__ballot(l2));
   }
   return delta;
 }
 
+// Reverse map (paper, "Method Summary" step 7): the output is C[m].
 template <int KT>
 __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, const uint32_t* kbuf,
-                                          int m) {
+                                          const uint16_t* crev, int m) {
   const long long o = (long long)gy * a.stride + gx;
-  if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)(kbuf[m] >> 16);
-  if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = (uint16_t)(kbuf[m] >> 16);
+  if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)crev[m];
+  if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = crev[m];
   if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m]);
 }
 
@@ -324,8 +342,10 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 template <int KT, int SHAPE, int IMAX>
 __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned char* smem) {
   const int T = a.T;
-  uint32_t* kbuf = reinterpret_cast<uint32_t*>(smem);
-  uint16_t* pbuf = reinterpret_cast<uint16_t*>(smem + a.off_p);
+  uint32_t* kbuf = reinterpret_cast<uint32_t*>(smem);                // sort exchange / f32 C
+  uint16_t* pbuf = reinterpret_cast<uint16_t*>(smem + a.off_p);      // f32 locations
+  uint16_t* om = KT == KEY_F32 ? pbuf : reinterpret_cast<uint16_t*>(smem);   // omnigram
+  uint16_t* crev = reinterpret_cast<uint16_t*>(smem + a.off_C);      // u8/u16 reverse map
   uint16_t* cnt = reinterpret_cast<uint16_t*>(smem + a.off_B);
   uint16_t* I = reinterpret_cast<uint16_t*>(smem + a.off_B);
   uint32_t* hist_all = reinterpret_cast<uint32_t*>(smem + a.off_hist);
@@ -391,15 +411,17 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
 
   // 2. ordinal transform
   if (KT == KEY_U8)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, cnt, wsum);
+    block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, om, crev, cnt, wsum);
   else if (KT == KEY_U16)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, cnt, wsum);
+    block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, om, crev, cnt, wsum);
   else
-    block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, cnt, wsum);
+    block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, om, crev, cnt, wsum);
 
+  // omnigram padding: locations outside the box (box width < 256)
+  if (t < 16) om[T + t] = 0xffff;
   // 3. ordinal image (overwrites the sort's count table)
   for (int v = t; v < T; v += kThreads) {
-    const uint32_t loc = omega_at<KT>(kbuf, pbuf, v);
+    const uint32_t loc = (uint32_t)om[v];
     I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
   }
   __syncthreads();
@@ -407,7 +429,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
 
   // 4. bands
   const int k = a.rank;
-  uint32_t* hist = hist_all + wid * 256;
+  uint32_t* hist = hist_all + wid * 128;
   int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;
   const int seg = lane / tw, col = lane - seg * tw;
@@ -419,13 +441,16 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   // 4a. seed + first row of each band, one segment at a time
   for (int s = 0; s < segs; ++s) {
     const int cy = (wid * segs + s) * R - a.dy_min;
-    int ms = seed_solve<KT, SHAPE>(0 - a.dx_min, cy, a, kbuf, pbuf, I, hist, rsp, blocks);
+    int ms = seed_solve<KT, SHAPE>(0 - a.dx_min, cy, a, om, I, hist, rsp, blocks);
     ++seeds;
     m = set_lane(ms, s * tw, m);
     for (int c = 1; c < tw; ++c) {
       const int cxp = c - 1 - a.dx_min;
+      const uint32_t pre_up = om[min(ms + lane, T - 1)];
+      const uint32_t pre_dn = om[max(ms - 64 + lane, 0)];
       const int cnt_new = k + hstep_delta(cxp, cy, ms, a, I, hrow);
-      ms = scan_select<KT, SHAPE>(ms, cnt_new, k, cxp + 1, cy, a, kbuf, pbuf, rsp, blocks);
+      ms = scan_core<SHAPE>(ms, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), a, om,
+                            rsp, blocks, pre_up, pre_dn);
       m = set_lane(ms, s * tw + c, m);
     }
   }
@@ -433,7 +458,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   const long long clk2 = a.counters ? (long long)clock64() : 0;
   {
     const int gx = tx0 + col, gy = ty0 + row0;
-    if (lane < segs * tw && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, m);
+    if (lane < segs * tw && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m);
   }
 
   // 4b. vertical sweep down each band
@@ -443,6 +468,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     const int lbase = cy_prev * a.pitch + cxl;
     int delta = 0;
     if (lane_active) {
+#pragma unroll 4
       for (int j = 0; j < a.ncols; ++j) {
         const int4 o = vtab[j];
         delta += (int)(I[lbase + o.x] < m) - (int)(I[lbase + o.y] < m);
@@ -452,7 +478,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     int mnew = m;
     const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
     if (lane_active)
-      mnew = lane_select<KT, SHAPE>(pl, cl, k, cxy, kLaneBudget, a, kbuf, pbuf, rsp, groups);
+      mnew = lane_select<SHAPE>(pl, cl, k, cxy, kLaneBudget, a, om, rsp, groups);
     uint64_t left = __ballot(lane_active && mnew < 0);
     while (left) {
       const int L = __ffsll((unsigned long long)left) - 1;
@@ -460,12 +486,12 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
       const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
       const int mL = scan_select<KT, SHAPE>(__builtin_amdgcn_readlane(pl, L),
                                             __builtin_amdgcn_readlane(cl, L), k, cxyL & 0xffff,
-                                            cxyL >> 16, a, kbuf, pbuf, rsp, blocks);
+                                            cxyL >> 16, a, om, rsp, blocks);
       mnew = set_lane(mL, L, mnew);
     }
     m = mnew;
     const int gx = tx0 + col, gy = ty0 + row0 + r;
-    if (lane_active && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, m);
+    if (lane_active && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m);
   }
 
   if (a.counters && lane == 0) {
