@@ -63,8 +63,10 @@ const char* mf_status_string(int status);
  * rasterised once into integer row spans; the GPU never evaluates geometry.
  * It must be row- and column-convex (each row and column of the window is
  * one run of pixels), which holds for every convex shape; the constructors
- * return MF_ERR_UNSUPPORTED otherwise.  Its extent is limited to 255 pixels
- * in each direction from the centre.  The library uploads the spans to each
+ * return MF_ERR_UNSUPPORTED otherwise.  Its offsets are limited to 255 in
+ * each direction from the centre; the filter itself needs the window's
+ * width and height to be at most 247 pixels (a disc of radius <= 123) and
+ * returns MF_ERR_UNSUPPORTED beyond.  The library uploads the spans to each
  * device the first time the footprint is used there and keeps that copy
  * until mf_footprint_destroy.
  * ------------------------------------------------------------------------ */
@@ -122,6 +124,55 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Batched filtering (not in the paper): many images of any sizes, dtypes
+ * and footprints in one persistent launch.
+ *
+ * mf_plan_create validates every entry (as median_filter does, plus no
+ * output may overlap any input or other output: MF_ERR_ALIAS), plans each
+ * image (the tuned tile shape for its dtype and footprint when the tuned
+ * table has one -- loaded first from `tune_cache_path` if not NULL -- else
+ * the default choice), and allocates the device tables: a descriptor per
+ * image, one queue of all tiles ordered longest-estimated-first, two queue
+ * counters and, if some image needs it, global scratch.  The plan keeps the
+ * buffer pointers of `descs` (the device images themselves are not copied):
+ * they must stay valid for every launch.  The footprints must outlive the
+ * plan.  Synchronous.
+ *
+ * mf_plan_launch queues one persistent kernel on `stream`: CUs x occupancy
+ * workgroups pop tiles until the queue is empty; the last one resets the
+ * counters, so launches need no memset, allocate nothing, and may be
+ * captured in a graph.  Launches of one plan must not overlap in time.
+ *
+ * mf_plan_capture captures mf_plan_launch on `stream` (not the null
+ * stream) into a hipGraph owned by the plan; mf_plan_replay launches that
+ * graph on `stream`.
+ *
+ * median_filter_batched = create + launch + stream synchronize + destroy.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  const void* img; /* device */
+  void* out;       /* device, same stride as img */
+  int w, h;
+  size_t stride_bytes;
+  int dtype;       /* mf_dtype */
+  const mf_footprint* fp;
+  int boundary;    /* mf_boundary */
+} mf_image_desc;
+
+typedef struct mf_plan mf_plan;
+
+int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_path,
+                   mf_plan** out);
+int mf_plan_launch(mf_plan* plan, hipStream_t stream);
+int mf_plan_capture(mf_plan* plan, hipStream_t stream);
+int mf_plan_replay(mf_plan* plan, hipStream_t stream);
+/* Total tiles, workgroups per launch, LDS bytes per workgroup, scratch bytes. */
+int mf_plan_info(const mf_plan* plan, int* tiles, int* grid, int* lds_bytes,
+                 long long* scratch_bytes);
+void mf_plan_destroy(mf_plan* plan);
+int median_filter_batched(const mf_image_desc* descs, int n, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Tile-shape control, for measurement and tuning.  tile_w/tile_h are the
  * output tile size: tile_w in {8, 16, 32, 64} and tile_h a multiple of
  * 16 * (64 / tile_w) (16 waves, each owning 64/tile_w bands of equal
@@ -141,6 +192,27 @@ int mf_set_tile_override(int tile_w, int tile_h);
  * (synchronous).  Not thread-safe against concurrent filter calls.
  * Counting adds a few scalar instructions per block. */
 int mf_work_counters(int enable, unsigned long long* out8);
+
+/* ------------------------------------------------------------------------
+ * Autotuner (not in the paper).  Times every valid tile shape of the plain
+ * filter for this (dtype, footprint) on the caller's image: img/out as in
+ * median_filter (device buffers; out is overwritten), `reps` timed runs per
+ * shape after one warm-up, on `stream` (synchronous: returns when timing
+ * is done).  The fastest shape is recorded in the library's tuned-shape
+ * table, which later plain calls and batched plans consult for the same
+ * dtype and footprint.  Outputs (any may be NULL): the shape and its mean
+ * time in milliseconds.
+ * ------------------------------------------------------------------------ */
+int mf_autotune(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                const mf_footprint* fp, int boundary, void* out, hipStream_t stream, int reps,
+                int* best_tile_w, int* best_tile_h, float* best_ms);
+
+/* Tuned-shape table persistence: a JSON array, one object per line with
+ * "key", "tile_w", "tile_h", "ms".  Load merges into the table (existing
+ * keys are replaced); save writes the whole table.  MF_ERR_INVALID_ARG if
+ * the file cannot be opened. */
+int mf_tune_cache_load(const char* path);
+int mf_tune_cache_save(const char* path);
 
 /* The tile shape and launch the plain filter would use for this image and
  * footprint: output tile size, input box size (tile + window extent) and

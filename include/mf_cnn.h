@@ -1,0 +1,80 @@
+/*
+ * mf_cnn.h -- kernels of the bracket-proposal network (not in the paper).
+ *
+ * A small CNN predicts, per 8x8-pixel cell, a value bracket [lo, hi] meant
+ * to contain the medians of the cell's pixels; the exact filter then ranks
+ * only the pixels inside a tile's bracket (median_filter_learned).  These
+ * entry points expose the network's kernels for training and testing.
+ * All pointers are DEVICE pointers; calls are asynchronous on `stream`;
+ * argument errors return MF_ERR_INVALID_ARG before anything is queued.
+ *
+ * Layouts: activations bf16 [H][W][32] (32 channels per cell); weights bf16
+ * [cout][9][32] with tap = 3 * (dy + 1) + (dx + 1); bias f32 [cout].
+ * cout is 32 (hidden layers) or 16 (output layer: channel 0 = lo, 1 = hi).
+ * Convolutions are 3x3, stride 1, zero padding, bf16 x bf16 products summed
+ * in float32 on MFMA.
+ */
+#ifndef MF_CNN_H
+#define MF_CNN_H
+
+#include <stddef.h>
+
+#include "median_filter.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One 16x32 by 32x16 bfloat16 matrix product on the MFMA unit (row-major
+ * inputs and output, D f32), for checking the operand layout. */
+int mf_mfma_probe(const void* a, const void* b, float* d, hipStream_t stream);
+
+/* y = conv3x3(x, w) + bias with an epilogue:
+ *   mode 0: bf16 [H][W][32] = relu(.)               (cout must be 32)
+ *   mode 1: f32 [H][W][cout] = (.)                  (cout 16 or 32)
+ *   mode 2: bf16 [H][W][32] = (.) * [mask > 0], mask a bf16 activation,
+ *           bias may be NULL (backward data through a ReLU; cout 32).
+ * cout == 16 always writes f32 (mode is ignored but must be 1). */
+int mf_cnn_conv_forward(const void* x, int H, int W, const void* w, const float* bias, int cout,
+                        int mode, const void* mask, void* y, hipStream_t stream);
+
+/* Weights for backward data: wf[ci][t][co] = w[co][8 - t][ci] (co < cout,
+ * else 0); wf is bf16 [32][9][32].  Then dX = mf_cnn_conv_forward(dY, wf). */
+int mf_cnn_flip_weights(const void* w, int cout, void* wf, hipStream_t stream);
+
+/* Weight and bias gradients: dw[co][t][ci] = sum_cells dy[cell][co] *
+ * x[cell + offset(t)][ci], db[co] = sum_cells dy[cell][co] (f32).  x and dy
+ * are bf16 [H][W][32] (dy channels >= cout ignored).  Split over blocks of
+ * segs_per_block 32-cell row segments into `workspace` (floats; size from
+ * mf_cnn_wgrad_workspace), then reduced in a fixed order (deterministic). */
+long long mf_cnn_wgrad_workspace(int H, int W, int cout, int segs_per_block);
+int mf_cnn_conv_wgrad(const void* x, const void* dy, int H, int W, int cout, int segs_per_block,
+                      float* workspace, float* dw, float* db, hipStream_t stream);
+
+/* Pinball loss of out[cell][0] (lo) and out[cell][1] (hi) (f32, out_ch
+ * floats per cell) against tgt[cell][2]: writes d(sum of losses)/d(out) as
+ * bf16 [ncell][32] (channels 2..31 zero) and per-256-cell partial sums of
+ * the loss to part_loss[ceil(ncell / 256)]. */
+int mf_cnn_pinball(const float* out, int out_ch, const float* tgt, int ncell, float tau_lo,
+                   float tau_hi, void* dout, float* part_loss, hipStream_t stream);
+
+/* Network input per 8x8 cell (bf16 [ceil(h/8)][ceil(w/8)][32]): channel 0 =
+ * mean pixel value / 255 (u8) or / 65535 (u16), channel 1 = radius / 64. */
+int mf_cnn_features(const void* img, int w, int h, size_t stride_bytes, int dtype, int radius,
+                    void* feat, hipStream_t stream);
+
+/* Training targets per cell (f32 [cells][2]): min and max of the median
+ * image over the cell, divided by 255 or 65535. */
+int mf_cnn_targets(const void* med, int w, int h, size_t stride_bytes, int dtype, float* tgt,
+                   hipStream_t stream);
+
+/* Adam step (step >= 1) on n float32 parameters with their moments; also
+ * writes the bf16 copy p_bf16 (may be NULL). */
+int mf_cnn_adam(float* p, float* m, float* v, const float* grad, int n, float lr, float b1,
+                float b2, float eps, int step, void* p_bf16, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_CNN_H */

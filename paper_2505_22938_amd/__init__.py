@@ -57,6 +57,27 @@ def lib():
         "mf_set_tile_override": ([I, I], I),
         "mf_query_plan": ([I, I, I, P, IP, IP, IP, IP, IP], I),
         "mf_work_counters": ([I, P], I),
+        "mf_autotune": ([P, I, I, SZ, I, P, I, P, P, I, IP, IP,
+                         ctypes.POINTER(ctypes.c_float)], I),
+        "mf_tune_cache_load": ([ctypes.c_char_p], I),
+        "mf_plan_create": ([P, I, ctypes.c_char_p, PP], I),
+        "mf_plan_launch": ([P, P], I),
+        "mf_plan_capture": ([P, P], I),
+        "mf_plan_replay": ([P, P], I),
+        "mf_plan_info": ([P, IP, IP, IP, ctypes.POINTER(ctypes.c_longlong)], I),
+        "mf_plan_destroy": ([P], None),
+        "median_filter_batched": ([P, I, P], I),
+        "mf_mfma_probe": ([P, P, P, P], I),
+        "mf_cnn_conv_forward": ([P, I, I, P, P, I, I, P, P, P], I),
+        "mf_cnn_flip_weights": ([P, I, P, P], I),
+        "mf_cnn_wgrad_workspace": ([I, I, I, I], ctypes.c_longlong),
+        "mf_cnn_conv_wgrad": ([P, P, I, I, I, I, P, P, P, P], I),
+        "mf_cnn_pinball": ([P, I, P, I, ctypes.c_float, ctypes.c_float, P, P, P], I),
+        "mf_cnn_features": ([P, I, I, SZ, I, I, P, P], I),
+        "mf_cnn_targets": ([P, I, I, SZ, I, P, P], I),
+        "mf_cnn_adam": ([P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, I, P, P], I),
+        "mf_tune_cache_save": ([ctypes.c_char_p], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -213,8 +234,155 @@ def work_counters(enable: int):
     return list(buf) if enable < 0 else None
 
 
+def autotune(img, fp: Footprint, boundary: str = "clamp", out=None, reps: int = 3, stream=None):
+    """Time every tile shape for this dtype and footprint on `img`; the
+    fastest is used by later calls.  Returns (tile_w, tile_h, ms)."""
+    import torch
+    code, es, w, h, stride_bytes = _plane_args(img)
+    if out is None:
+        out = torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+    tw, th, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check("mf_autotune", lib().mf_autotune(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes,
+                                            code, fp.handle, BOUNDARY[boundary],
+                                            ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream),
+                                            int(reps), ctypes.byref(tw), ctypes.byref(th),
+                                            ctypes.byref(ms)))
+    return tw.value, th.value, ms.value
+
+
+def tune_cache_load(path: str):
+    _check("mf_tune_cache_load", lib().mf_tune_cache_load(path.encode()))
+
+
+def tune_cache_save(path: str):
+    _check("mf_tune_cache_save", lib().mf_tune_cache_save(path.encode()))
+
+
 def query_plan(w: int, h: int, dtype: int, fp: Footprint):
     vals = [ctypes.c_int() for _ in range(5)]
     _check("mf_query_plan", lib().mf_query_plan(w, h, dtype, fp.handle,
                                                 *[ctypes.byref(v) for v in vals]))
     return dict(zip(("tile_w", "tile_h", "box_w", "box_h", "lds_bytes"), (v.value for v in vals)))
+
+
+class _ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("w", ctypes.c_int),
+                ("h", ctypes.c_int), ("stride_bytes", ctypes.c_size_t), ("dtype", ctypes.c_int),
+                ("fp", ctypes.c_void_p), ("boundary", ctypes.c_int)]
+
+
+def _descs(items):
+    arr = (_ImageDesc * max(1, len(items)))()
+    for i, (img, out, fp, boundary) in enumerate(items):
+        code, es, w, h, stride_bytes = _plane_args(img)
+        if out.shape != img.shape or out.dtype != img.dtype or out.stride() != img.stride():
+            raise ValueError("out must match img in shape, dtype and strides")
+        arr[i] = _ImageDesc(img.data_ptr(), out.data_ptr(), w, h, stride_bytes, code, fp.handle,
+                            BOUNDARY[boundary])
+    return arr
+
+
+class BatchPlan:
+    """A persistent batched launch over many (img, out, footprint, boundary)
+    entries; keep the tensors and footprints alive as long as the plan."""
+
+    def __init__(self, items, tune_cache: str | None = None):
+        self.items = list(items)
+        self._arr = _descs(self.items)
+        h = ctypes.c_void_p()
+        _check("mf_plan_create", lib().mf_plan_create(
+            ctypes.cast(self._arr, ctypes.c_void_p), len(self.items),
+            tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check("mf_plan_launch", lib().mf_plan_launch(self._h, _stream_ptr(stream)))
+
+    def capture(self, stream):
+        _check("mf_plan_capture", lib().mf_plan_capture(self._h, _stream_ptr(stream)))
+
+    def replay(self, stream):
+        _check("mf_plan_replay", lib().mf_plan_replay(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        t, g, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        s = ctypes.c_longlong()
+        _check("mf_plan_info", lib().mf_plan_info(self._h, ctypes.byref(t), ctypes.byref(g),
+                                                  ctypes.byref(l), ctypes.byref(s)))
+        return dict(tiles=t.value, grid=g.value, lds_bytes=l.value, scratch_bytes=s.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.mf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def median_filter_batched(items, stream=None):
+    """Filter every (img, out, footprint, boundary) entry in one persistent launch."""
+    arr = _descs(list(items))
+    _check("median_filter_batched", lib().median_filter_batched(
+        ctypes.cast(arr, ctypes.c_void_p), len(items), _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Bracket-proposal CNN kernels (include/mf_cnn.h)
+# ---------------------------------------------------------------------------
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class cnn:
+    """Thin wrappers of the CNN kernels; tensors are device tensors whose
+    dtype holds the right bytes (bf16 data may be passed as torch.bfloat16
+    or as raw uint16)."""
+
+    @staticmethod
+    def mfma_probe(a, b, d, stream=None):
+        _check("mf_mfma_probe", lib().mf_mfma_probe(_p(a), _p(b), _p(d), _stream_ptr(stream)))
+
+    @staticmethod
+    def conv_forward(x, H, W, w, bias, cout, mode, y, mask=None, stream=None):
+        _check("mf_cnn_conv_forward", lib().mf_cnn_conv_forward(
+            _p(x), H, W, _p(w), _p(bias), cout, mode, _p(mask), _p(y), _stream_ptr(stream)))
+
+    @staticmethod
+    def flip_weights(w, cout, wf, stream=None):
+        _check("mf_cnn_flip_weights", lib().mf_cnn_flip_weights(_p(w), cout, _p(wf),
+                                                                 _stream_ptr(stream)))
+
+    @staticmethod
+    def wgrad_workspace(H, W, cout, segs_per_block=8):
+        return int(lib().mf_cnn_wgrad_workspace(H, W, cout, segs_per_block))
+
+    @staticmethod
+    def conv_wgrad(x, dy, H, W, cout, workspace, dw, db, segs_per_block=8, stream=None):
+        _check("mf_cnn_conv_wgrad", lib().mf_cnn_conv_wgrad(
+            _p(x), _p(dy), H, W, cout, segs_per_block, _p(workspace), _p(dw), _p(db),
+            _stream_ptr(stream)))
+
+    @staticmethod
+    def pinball(out, out_ch, tgt, ncell, tau_lo, tau_hi, dout, part_loss, stream=None):
+        _check("mf_cnn_pinball", lib().mf_cnn_pinball(_p(out), out_ch, _p(tgt), ncell, tau_lo,
+                                                      tau_hi, _p(dout), _p(part_loss),
+                                                      _stream_ptr(stream)))
+
+    @staticmethod
+    def features(img, radius, feat, stream=None):
+        code, es, w, h, sb = _plane_args(img)
+        _check("mf_cnn_features", lib().mf_cnn_features(_p(img), w, h, sb, code, radius,
+                                                        _p(feat), _stream_ptr(stream)))
+
+    @staticmethod
+    def targets(med, tgt, stream=None):
+        code, es, w, h, sb = _plane_args(med)
+        _check("mf_cnn_targets", lib().mf_cnn_targets(_p(med), w, h, sb, code, _p(tgt),
+                                                      _stream_ptr(stream)))
+
+    @staticmethod
+    def adam(p, m, v, grad, lr, step, p_bf16=None, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _check("mf_cnn_adam", lib().mf_cnn_adam(_p(p), _p(m), _p(v), _p(grad), p.numel(), lr, b1,
+                                                b2, eps, step, _p(p_bf16), _stream_ptr(stream)))

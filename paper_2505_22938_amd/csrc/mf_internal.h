@@ -1,8 +1,11 @@
 // Internal declarations shared by the library's host sources.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/median_filter.h"
@@ -27,6 +30,75 @@ struct mf_footprint {
 };
 
 namespace mf {
+
+constexpr int kThreads = 1024;            // threads per tile workgroup
+constexpr int kWaves = kThreads / 64;     // wave64
+constexpr int kDigits = 16;               // 4-bit radix digits
+constexpr int kCounterBytes = kDigits * kThreads * 2;
+
+enum { KEY_U8 = 0, KEY_U16 = 1, KEY_F32 = 2 };
+enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };
+
+// Everything one tile needs to know about its image and plan.  Passed by
+// value to the plain kernels and stored in the batched descriptor table.
+struct ImageDesc {
+  const void* img;
+  void* out;
+  long long stride;  // elements (image and output)
+  int w, h, boundary;
+  int tw, th, tiles_x, tiles_y;
+  int bw, bh, T, pitch;
+  int dx_min, dy_min, nrows, ncols;
+  int rank, limit;
+  int segs, band_rows, hist_shift;
+  const short2* spans;  // nrows row spans (index dy - dy_min) then ncols column spans
+  // LDS layout, bytes
+  int off_p, off_C, off_B, off_hist, off_tab, lds_bytes;
+  unsigned long long* counters;  // optional work counters (null: off)
+  // global-scratch variant: per-workgroup slot of slot_bytes at scratch
+  unsigned char* scratch;
+  long long slot_bytes;
+  int off_x1, off_lr, ipt;
+  // kernel selection: key type, shape, 1 = global-scratch variant, and the
+  // register capacity (elements per thread) of the LDS variant
+  int kt, shape, gs, imax;
+};
+
+struct DeviceInfo {
+  int lds_max = 0;
+  int cus = 0;
+};
+int device_info(int dev, DeviceInfo* out);
+
+// Tile plans.  make_plan: everything in LDS; make_plan_gs: sort, omnigram and
+// reverse map in a global scratch slot.  choose_plan picks the tuned shape
+// for this (dtype, footprint) if one is recorded, else the widest layout
+// that fits, LDS first; imax_cap bounds the register capacity of LDS plans.
+int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
+int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
+int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d);
+// Enumerate every valid plan (for the autotuner).
+std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int lds_max,
+                                       int imax_cap);
+// Fill the per-image fields of a plan.
+void bind_image(ImageDesc* d, const void* img, int w, int h, size_t stride_bytes, int dtype,
+                const mf_footprint* fp, int boundary, int rank, const void* spans);
+
+int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                   const mf_footprint* fp, int boundary, const void* out);
+
+// Global scratch cached per (device, stream).
+int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out);
+
+// Tuned tile shapes, keyed by dtype and footprint.
+std::string tune_key(int dtype, const mf_footprint* fp);
+bool tuned_shape(int dtype, const mf_footprint* fp, int* tw, int* th);
+void record_tuned_shape(int dtype, const mf_footprint* fp, int tw, int th, double ms);
+int tune_cache_load(const char* path);
+int tune_cache_save(const char* path);
+
+// Tile-shape override (measurement): 0 = off.
+void get_override(int* tw, int* th);
 
 // Upload (once per device) and return the device span table of `fp`:
 // [row (lo,hi) pairs as int16][column (lo,hi) pairs as int16].

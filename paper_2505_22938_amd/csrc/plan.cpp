@@ -1,0 +1,367 @@
+// Host-side planning: tile geometry, LDS and scratch layout, the tuned-shape
+// table and its JSON cache, the per-(device, stream) scratch cache.
+//
+// A plan fixes the output tile (tw x th), the input box (tile grown by the
+// window extent, paper "Method Summary" step 1: input tiles padded by the
+// filter radius), the band layout of the 16 waves and where each per-tile
+// structure lives.  Input boxes are limited to 255 x 256 pixels so a box
+// location fits the omnigram's 8+8-bit encoding (paper, "Implementation":
+// input tiles up to 256x256, 16-bit omnigram entries) and (255, 255) lies
+// outside every box (the omnigram's padding location).
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+namespace {
+
+constexpr int kItemChoices[] = {9, 17, 25, 33};
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+std::mutex g_override_mu;
+int g_tile_w = 0, g_tile_h = 0;
+
+// Band layout shared by both variants; fills geometry fields.
+int band_geometry(const mf_footprint* fp, int tw, int th, ImageDesc* d) {
+  if (tw < 1 || tw > 64 || 64 % tw) return MF_ERR_UNSUPPORTED;
+  const int segs = 64 / tw;
+  if (th < 1 || th % (kWaves * segs)) return MF_ERR_UNSUPPORTED;
+  const int R = th / (kWaves * segs);
+  const int bw = tw + fp->dx_max - fp->dx_min, bh = th + fp->dy_max - fp->dy_min;
+  if (bw > 255 || bh > 256) return MF_ERR_UNSUPPORTED;
+  const int T = bw * bh;
+  if (T > 65535) return MF_ERR_UNSUPPORTED;
+  // ordinal-image row pitch (16-bit elements): pitch/2 odd, so consecutive
+  // rows start in different LDS banks
+  int pitch = round_up(bw, 2);
+  if ((pitch / 2) % 2 == 0) pitch += 2;
+  d->tw = tw;
+  d->th = th;
+  d->bw = bw;
+  d->bh = bh;
+  d->T = T;
+  d->pitch = pitch;
+  d->segs = segs;
+  d->band_rows = R;
+  int hs = 0;
+  while (((T - 1) >> hs) >= 256) ++hs;
+  d->hist_shift = hs;
+  d->dx_min = fp->dx_min;
+  d->dy_min = fp->dy_min;
+  d->nrows = (int)fp->row_lo.size();
+  d->ncols = (int)fp->col_lo.size();
+  d->limit = (int)fp->limit;
+  d->shape = fp->kind == 0 ? SHAPE_DISC : SHAPE_SPANS;
+  return MF_OK;
+}
+
+int table_bytes(const ImageDesc* d) {
+  const int nr4 = round_up(d->nrows, 4);
+  return 64 + 4 * nr4 + 8 * nr4 + 16 * d->ncols;
+}
+
+}  // namespace
+
+int device_info(int dev, DeviceInfo* out) {
+  static std::mutex mu;
+  static DeviceInfo cache[64];
+  static bool have[64] = {};
+  if (dev < 0 || dev >= 64) return MF_ERR_HIP;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[dev]) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MF_ERR_HIP;
+    cache[dev].lds_max = (int)prop.sharedMemPerBlock;
+    cache[dev].cus = prop.multiProcessorCount;
+    have[dev] = true;
+  }
+  *out = cache[dev];
+  return MF_OK;
+}
+
+int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d) {
+  int rc = band_geometry(fp, tw, th, d);
+  if (rc) return rc;
+  const int T = d->T;
+  const int need_items = ((T + kThreads - 1) / kThreads) | 1;
+  int im = 0;
+  for (int c : kItemChoices)
+    if (need_items <= c) {
+      im = c;
+      break;
+    }
+  if (!im) return MF_ERR_UNSUPPORTED;
+  // region A: sort exchange (u32 words); afterwards omega and C (8/16-bit
+  // keys: two 16-bit arrays of T + 16 padding entries each) or C32 + omega
+  // (float keys).  Region B: digit counts during the sort, afterwards the
+  // ordinal image and the per-wave seed histograms.
+  const int TP = round_up(T, 8) + 16;
+  const int kb = dtype == MF_F32 ? 4 * round_up(T, 4) : 4 * TP;
+  const int pb = dtype == MF_F32 ? 2 * TP : 0;
+  const int ib = round_up(2 * d->pitch * d->bh, 16);
+  const int hb = kWaves * 128 * 4;
+  const int B = std::max(kCounterBytes, ib + hb);
+  d->off_p = kb;
+  d->off_C = 2 * TP;
+  d->off_B = kb + pb;
+  d->off_hist = d->off_B + ib;
+  d->off_tab = d->off_B + B;
+  d->lds_bytes = d->off_tab + table_bytes(d);
+  d->kt = dtype;
+  d->gs = 0;
+  d->imax = im;
+  d->slot_bytes = 0;
+  d->off_x1 = d->off_lr = d->ipt = 0;
+  if (d->lds_bytes > lds_max) return MF_ERR_UNSUPPORTED;
+  return MF_OK;
+}
+
+int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d) {
+  int rc = band_geometry(fp, tw, th, d);
+  if (rc) return rc;
+  const int T = d->T;
+  const int TP = round_up(T, 8) + 16;
+  const int ib = round_up(2 * d->pitch * d->bh, 16);
+  const int hb = kWaves * 128 * 4;
+  const int B = std::max(kCounterBytes, ib + hb);
+  // slot: x0 (8 TP bytes of 64-bit words; after the sort omega + C16, or
+  // C32 + omega), x1 (8 TP), per-element byte ranks (T)
+  d->off_p = 4 * TP;
+  d->off_C = dtype == MF_F32 ? 0 : 2 * TP;
+  d->off_x1 = 8 * TP;
+  d->off_lr = 16 * TP;
+  d->slot_bytes = round_up(16 * TP + T, 256);
+  d->ipt = (T + kThreads - 1) / kThreads;
+  d->off_B = 0;
+  d->off_hist = ib;
+  d->off_tab = B;
+  d->lds_bytes = B + table_bytes(d);
+  d->kt = dtype;
+  d->gs = 1;
+  d->imax = 0;
+  if (d->lds_bytes > lds_max) return MF_ERR_UNSUPPORTED;
+  return MF_OK;
+}
+
+void get_override(int* tw, int* th) {
+  std::lock_guard<std::mutex> lock(g_override_mu);
+  *tw = g_tile_w;
+  *th = g_tile_h;
+}
+
+static int plan_shape(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, int tw,
+                      int th, ImageDesc* d) {
+  if (make_plan(dtype, fp, lds_max, tw, th, d) == MF_OK && d->imax <= imax_cap) return MF_OK;
+  return make_plan_gs(dtype, fp, lds_max, tw, th, d);
+}
+
+int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d) {
+  int tw = 0, th = 0;
+  get_override(&tw, &th);
+  if (tw > 0) return plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d);
+  if (tuned_shape(dtype, fp, &tw, &th) &&
+      plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d) == MF_OK)
+    return MF_OK;
+  static const int tws[] = {64, 32, 16, 8};
+  for (int w : tws) {
+    const int segs = 64 / w;
+    for (int R = 8; R >= 1; R /= 2)
+      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK && d->imax <= imax_cap)
+        return MF_OK;
+  }
+  for (int w : tws) {
+    const int segs = 64 / w;
+    for (int R = 8; R >= 1; R /= 2)
+      if (make_plan_gs(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK) return MF_OK;
+  }
+  return MF_ERR_UNSUPPORTED;
+}
+
+std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int lds_max,
+                                       int imax_cap) {
+  std::vector<ImageDesc> out;
+  static const int tws[] = {64, 32, 16, 8};
+  for (int w : tws) {
+    const int segs = 64 / w;
+    for (int R = 1; R <= 16; R *= 2) {
+      ImageDesc d{};
+      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, &d) == MF_OK && d.imax <= imax_cap)
+        out.push_back(d);
+      else if (make_plan_gs(dtype, fp, lds_max, w, kWaves * segs * R, &d) == MF_OK)
+        out.push_back(d);
+    }
+  }
+  return out;
+}
+
+void bind_image(ImageDesc* d, const void* img, int w, int h, size_t stride_bytes, int dtype,
+                const mf_footprint* fp, int boundary, int rank, const void* spans) {
+  (void)fp;
+  d->img = img;
+  d->w = w;
+  d->h = h;
+  d->stride = (long long)(stride_bytes / (size_t)elem_size(dtype));
+  d->boundary = boundary;
+  d->tiles_x = (w + d->tw - 1) / d->tw;
+  d->tiles_y = (h + d->th - 1) / d->th;
+  d->rank = rank;
+  d->spans = static_cast<const short2*>(spans);
+  d->counters = nullptr;
+  d->scratch = nullptr;
+}
+
+int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                   const mf_footprint* fp, int boundary, const void* out) {
+  if (dtype != MF_U8 && dtype != MF_U16 && dtype != MF_F32) return MF_ERR_INVALID_ARG;
+  if (boundary != MF_CLAMP && boundary != MF_MIRROR) return MF_ERR_INVALID_ARG;
+  if (!fp || w < 0 || h < 0) return MF_ERR_INVALID_ARG;
+  if (w == 0 || h == 0) return MF_OK;
+  if (!img || !out) return MF_ERR_INVALID_ARG;
+  const size_t es = (size_t)elem_size(dtype);
+  if (stride_bytes < (size_t)w * es || stride_bytes % es) return MF_ERR_INVALID_ARG;
+  const size_t span = stride_bytes * (size_t)(h - 1) + (size_t)w * es;
+  const uintptr_t a0 = (uintptr_t)img, b0 = (uintptr_t)out;
+  if (a0 < b0 + span && b0 < a0 + span) return MF_ERR_ALIAS;
+  return MF_OK;
+}
+
+// ------------------------------------------------------------------ scratch
+
+namespace {
+struct ScratchEntry {
+  int dev;
+  hipStream_t stream;
+  void* ptr;
+  size_t bytes;
+};
+std::mutex g_scratch_mu;
+std::vector<ScratchEntry> g_scratch;
+}  // namespace
+
+int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  for (auto& e : g_scratch) {
+    if (e.dev == dev && e.stream == stream) {
+      if (e.bytes < bytes) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return MF_ERR_HIP;
+        (void)hipFree(e.ptr);
+        e.ptr = nullptr;
+        e.bytes = 0;
+        if (hipMalloc(&e.ptr, bytes) != hipSuccess) return MF_ERR_NOMEM;
+        e.bytes = bytes;
+      }
+      *out = e.ptr;
+      return MF_OK;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return MF_ERR_NOMEM;
+  g_scratch.push_back({dev, stream, p, bytes});
+  *out = p;
+  return MF_OK;
+}
+
+// ------------------------------------------------------------------ tuning table
+
+namespace {
+struct Tuned {
+  int tw, th;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tune;
+}  // namespace
+
+// Key: dtype, footprint kind, squared limit (discs), extents, taps and a
+// hash of the spans, so different shapes never share an entry.
+std::string tune_key(int dtype, const mf_footprint* fp) {
+  unsigned long long h = 1469598103934665603ull;
+  for (size_t i = 0; i < fp->row_lo.size(); ++i) {
+    h = (h ^ (unsigned long long)(fp->row_lo[i] + 1024)) * 1099511628211ull;
+    h = (h ^ (unsigned long long)(fp->row_hi[i] + 1024)) * 1099511628211ull;
+  }
+  char buf[192];
+  std::snprintf(buf, sizeof buf, "%s/%s/L%lld/x%d:%d/y%d:%d/n%d/h%016llx",
+                dtype == MF_U8 ? "u8" : dtype == MF_U16 ? "u16" : "f32",
+                fp->kind == 0 ? "disc" : "spans", fp->kind == 0 ? fp->limit : -1LL, fp->dx_min,
+                fp->dx_max, fp->dy_min, fp->dy_max, fp->taps, h);
+  return buf;
+}
+
+bool tuned_shape(int dtype, const mf_footprint* fp, int* tw, int* th) {
+  const std::string k = tune_key(dtype, fp);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *tw = it->second.tw;
+  *th = it->second.th;
+  return true;
+}
+
+void record_tuned_shape(int dtype, const mf_footprint* fp, int tw, int th, double ms) {
+  const std::string k = tune_key(dtype, fp);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[k] = {tw, th, ms};
+}
+
+// Cache format: a JSON array with one object per line,
+//   {"key": "<tune_key>", "tile_w": 64, "tile_h": 128, "ms": 2.16}
+int tune_cache_load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return MF_ERR_INVALID_ARG;
+  char line[512];
+  int n = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    char key[256];
+    int tw = 0, th = 0;
+    double ms = 0;
+    const char* p = std::strstr(line, "\"key\"");
+    if (!p) continue;
+    if (std::sscanf(p, "\"key\": \"%255[^\"]\", \"tile_w\": %d, \"tile_h\": %d, \"ms\": %lf", key,
+                    &tw, &th, &ms) >= 3) {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tune[key] = {tw, th, ms};
+      ++n;
+    }
+  }
+  std::fclose(f);
+  return n >= 0 ? MF_OK : MF_ERR_INVALID_ARG;
+}
+
+int tune_cache_save(const char* path) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) return MF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::fprintf(f, "[\n");
+  size_t i = 0;
+  for (const auto& kv : g_tune) {
+    std::fprintf(f, "  {\"key\": \"%s\", \"tile_w\": %d, \"tile_h\": %d, \"ms\": %.4f}%s\n",
+                 kv.first.c_str(), kv.second.tw, kv.second.th, kv.second.ms,
+                 ++i < g_tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]\n");
+  std::fclose(f);
+  return MF_OK;
+}
+
+}  // namespace mf
+
+extern "C" int mf_set_tile_override(int tile_w, int tile_h) {
+  if (tile_w < 0 || tile_h < 0 || (tile_w == 0) != (tile_h == 0)) return MF_ERR_INVALID_ARG;
+  if (tile_w && (tile_w > 64 || 64 % tile_w || tile_w < 8 || tile_h > 256 ||
+                 tile_h % (16 * (64 / tile_w))))
+    return MF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(mf::g_override_mu);
+  mf::g_tile_w = tile_w;
+  mf::g_tile_h = tile_h;
+  return MF_OK;
+}

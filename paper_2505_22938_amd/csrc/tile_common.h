@@ -6,15 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mf_internal.h"
+
 namespace mf {
-
-enum { KEY_U8 = 0, KEY_U16 = 1, KEY_F32 = 2 };
-enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };
-
-constexpr int kThreads = 1024;            // threads per tile workgroup
-constexpr int kWaves = kThreads / 64;     // wave64
-constexpr int kDigits = 16;               // 4-bit radix digits
-constexpr int kCounterBytes = kDigits * kThreads * 2;
 
 // Boundary rule: clamp repeats the edge pixel; mirror reflects about it
 // without repeating it and folds with period 2(n-1).
@@ -166,6 +160,84 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
         if (PAYLOAD) pos[i] = q;
       }
     }
+  }
+}
+
+// Radix sort of one tile through global memory, for boxes whose sort does
+// not fit in LDS.  Same LSD scheme and stability argument as
+// block_radix_sort, but elements are not held in registers: each pass reads
+// its input from one of two global buffers (ping-pong), recounts, and
+// scatters into the other; the per-element local rank is kept in a byte
+// array.  Elements are 64-bit words (key << 16 | location); the key occupies
+// bits [16 + shift0, 16 + shift0 + 4*passes).  `passes` is even, so the
+// final pass writes the x0 region: locations to omega[] and keys to
+// crev16[] (16-bit keys) or crev32[] (32-bit keys).  ipt = elements per
+// thread (ceil(T / kThreads)); elements are numbered blocked (thread t owns
+// [t*ipt, (t+1)*ipt)).
+__device__ __forceinline__ void global_radix_sort(uint64_t* x0, uint64_t* x1, uint8_t* lrank,
+                                                  int T, int ipt, int shift0, int passes,
+                                                  uint16_t* omega, uint16_t* crev16,
+                                                  uint32_t* crev32, uint16_t* cnt,
+                                                  uint32_t* wsum) {
+  const int t = threadIdx.x;
+  const int e0 = t * ipt, e1 = min(T, e0 + ipt);
+  for (int pass = 0; pass < passes; ++pass) {
+    const uint64_t* src = (pass & 1) ? x1 : x0;
+    uint64_t* dst = (pass & 1) ? x0 : x1;
+    const int sh = 16 + shift0 + 4 * pass;
+    const bool last = pass + 1 == passes;
+    uint32_t c[16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) c[d] = 0;
+    for (int e = e0; e < e1; ++e) {
+      const uint32_t d = (uint32_t)(src[e] >> sh) & 15u;
+      uint32_t r = 0;
+#pragma unroll
+      for (int dd = 0; dd < 16; ++dd) {
+        if (dd == (int)d) {
+          r = c[dd];
+          c[dd] = r + 1;
+        }
+      }
+      lrank[e] = (uint8_t)r;
+    }
+#pragma unroll
+    for (int d = 0; d < 16; ++d) cnt[d * kThreads + t] = (uint16_t)c[d];
+    __syncthreads();
+    {
+      uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
+      uint4 a = row[0], b = row[1];
+      uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      uint32_t run = 0, ex[16];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t lo = w[j] & 0xffffu, hi = w[j] >> 16;
+        ex[2 * j] = run;
+        run += lo;
+        ex[2 * j + 1] = run;
+        run += hi;
+      }
+      const uint32_t base = block_exclusive_scan(run, wsum);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        w[j] = ((ex[2 * j] + base) & 0xffffu) | ((ex[2 * j + 1] + base) << 16);
+      row[0] = make_uint4(w[0], w[1], w[2], w[3]);
+      row[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+    __syncthreads();
+    for (int e = e0; e < e1; ++e) {
+      const uint64_t v = src[e];
+      const uint32_t d = (uint32_t)(v >> sh) & 15u;
+      const uint32_t o = (uint32_t)cnt[d * kThreads + t] + lrank[e];
+      if (!last) {
+        dst[o] = v;
+      } else {
+        omega[o] = (uint16_t)v;
+        if (crev32) crev32[o] = (uint32_t)(v >> 16);
+        else crev16[o] = (uint16_t)(v >> 16);
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -34,21 +34,6 @@
 
 namespace mf {
 
-struct ImageDesc {
-  const void* img;
-  void* out;
-  long long stride;  // elements (image and output)
-  int w, h, boundary;
-  int tw, th, tiles_x, tiles_y;
-  int bw, bh, T, pitch;
-  int dx_min, dy_min, nrows, ncols;
-  int rank, limit;
-  int segs, band_rows, hist_shift;
-  const short2* spans;  // nrows row spans (index dy - dy_min) then ncols column spans
-  // LDS layout, bytes
-  int off_p, off_C, off_B, off_hist, off_tab, lds_bytes;
-  unsigned long long* counters;  // optional work counters (null: off)
-};
 
 // Work counters (accumulated only when ImageDesc::counters is set).
 constexpr int kLaneBudget = 32;  // 8-ordinal groups a lane tests before the wave helps
@@ -339,13 +324,19 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 }
 
 // One output tile.  All threads of the workgroup must call it.
-template <int KT, int SHAPE, int IMAX>
-__device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned char* smem) {
+// GS = false: the sort, the omnigram and the reverse map live in LDS.
+// GS = true: they live in the workgroup's global scratch slot `gslot`
+// (boxes too large for LDS); the ordinal image, histograms and footprint
+// tables stay in LDS.
+template <int KT, int SHAPE, int IMAX, bool GS>
+__device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned char* smem,
+                                          unsigned char* gslot) {
   const int T = a.T;
-  uint32_t* kbuf = reinterpret_cast<uint32_t*>(smem);                // sort exchange / f32 C
-  uint16_t* pbuf = reinterpret_cast<uint16_t*>(smem + a.off_p);      // f32 locations
-  uint16_t* om = KT == KEY_F32 ? pbuf : reinterpret_cast<uint16_t*>(smem);   // omnigram
-  uint16_t* crev = reinterpret_cast<uint16_t*>(smem + a.off_C);      // u8/u16 reverse map
+  unsigned char* abase = GS ? gslot : smem;   // region holding the sorted arrays
+  uint32_t* kbuf = reinterpret_cast<uint32_t*>(abase);                // sort exchange / f32 C
+  uint16_t* pbuf = reinterpret_cast<uint16_t*>(abase + a.off_p);      // f32 locations
+  uint16_t* om = KT == KEY_F32 ? pbuf : reinterpret_cast<uint16_t*>(abase);   // omnigram
+  uint16_t* crev = reinterpret_cast<uint16_t*>(abase + a.off_C);      // u8/u16 reverse map
   uint16_t* cnt = reinterpret_cast<uint16_t*>(smem + a.off_B);
   uint16_t* I = reinterpret_cast<uint16_t*>(smem + a.off_B);
   uint32_t* hist_all = reinterpret_cast<uint32_t*>(smem + a.off_hist);
@@ -376,47 +367,67 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
                         (s.x - 1) * a.pitch + dx, s.y * a.pitch + dx);
   }
 
-  // 1. load the box (striped order)
-  uint32_t key[IMAX];
-  uint16_t pos[IMAX];
-  {
-    int lx = t % a.bw, ly = t / a.bw;
-    const int sx = kThreads % a.bw, sy = kThreads / a.bw;
-#pragma unroll
-    for (int i = 0; i < IMAX; ++i) {
-      const int e = i * kThreads + t;
-      uint32_t kk = 0, q = 0;
-      if (e < T) {
-        const int gx = remap(gx0 + lx, a.w, a.boundary);
-        const int gy = remap(gy0 + ly, a.h, a.boundary);
-        const long long off = (long long)gy * a.stride + gx;
-        const uint32_t p = (uint32_t)((ly << 8) | lx);
-        if (KT == KEY_U8) kk = ((uint32_t)static_cast<const uint8_t*>(a.img)[off] << 16) | p;
-        if (KT == KEY_U16) kk = ((uint32_t)static_cast<const uint16_t*>(a.img)[off] << 16) | p;
-        if (KT == KEY_F32) {
-          kk = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
-          q = p;
+  if constexpr (!GS) {
+    // 1. load the box (striped order)
+    uint32_t key[IMAX];
+    uint16_t pos[IMAX];
+    {
+      int lx = t % a.bw, ly = t / a.bw;
+      const int sx = kThreads % a.bw, sy = kThreads / a.bw;
+  #pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = i * kThreads + t;
+        uint32_t kk = 0, q = 0;
+        if (e < T) {
+          const int gx = remap(gx0 + lx, a.w, a.boundary);
+          const int gy = remap(gy0 + ly, a.h, a.boundary);
+          const long long off = (long long)gy * a.stride + gx;
+          const uint32_t p = (uint32_t)((ly << 8) | lx);
+          if (KT == KEY_U8) kk = ((uint32_t)static_cast<const uint8_t*>(a.img)[off] << 16) | p;
+          if (KT == KEY_U16) kk = ((uint32_t)static_cast<const uint16_t*>(a.img)[off] << 16) | p;
+          if (KT == KEY_F32) {
+            kk = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+            q = p;
+          }
+        }
+        key[i] = kk;
+        pos[i] = (uint16_t)q;
+        lx += sx;
+        ly += sy;
+        if (lx >= a.bw) {
+          lx -= a.bw;
+          ly += 1;
         }
       }
-      key[i] = kk;
-      pos[i] = (uint16_t)q;
-      lx += sx;
-      ly += sy;
-      if (lx >= a.bw) {
-        lx -= a.bw;
-        ly += 1;
-      }
     }
+
+    // 2. ordinal transform
+    if (KT == KEY_U8)
+      block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, om, crev, cnt, wsum);
+    else if (KT == KEY_U16)
+      block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, om, crev, cnt, wsum);
+    else
+      block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, om, crev, cnt, wsum);
+  } else {
+    // load the box straight into global scratch as 64-bit words
+    uint64_t* x0 = reinterpret_cast<uint64_t*>(gslot);
+    uint64_t* x1 = reinterpret_cast<uint64_t*>(gslot + a.off_x1);
+    for (int e = t; e < T; e += kThreads) {
+      const int ly = e / a.bw, lx = e - ly * a.bw;
+      const int gx = remap(gx0 + lx, a.w, a.boundary);
+      const int gy = remap(gy0 + ly, a.h, a.boundary);
+      const long long off = (long long)gy * a.stride + gx;
+      uint64_t kk;
+      if (KT == KEY_U8) kk = static_cast<const uint8_t*>(a.img)[off];
+      else if (KT == KEY_U16) kk = static_cast<const uint16_t*>(a.img)[off];
+      else kk = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+      x0[e] = (kk << 16) | (uint64_t)((ly << 8) | lx);
+    }
+    __syncthreads();
+    global_radix_sort(x0, x1, gslot + a.off_lr, T, a.ipt, 0, KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8,
+                      om, KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
+                      wsum);
   }
-
-  // 2. ordinal transform
-  if (KT == KEY_U8)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, om, crev, cnt, wsum);
-  else if (KT == KEY_U16)
-    block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, om, crev, cnt, wsum);
-  else
-    block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, om, crev, cnt, wsum);
-
   // omnigram padding: locations outside the box (box width < 256)
   if (t < 16) om[T + t] = 0xffff;
   // 3. ordinal image (overwrites the sort's count table)

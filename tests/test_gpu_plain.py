@@ -144,7 +144,28 @@ def sample_points(w, h, n, seed):
     return xs, ys
 
 
-@pytest.mark.parametrize("r", [8, 32])
+@pytest.mark.parametrize("r", [56, 64, 80, 100])
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+def test_plain_global_scratch_radius(mf, oracle_mod, r, dtype):
+    # boxes too large for LDS: sort, omnigram and reverse map in global scratch
+    img = make_img(dtype, 150, 130, 7)
+    got = run(mf, img, mf.Footprint.disc(r), "mirror")
+    assert_same(got, oracle_mod.filter(img, OF.disc(r), "mirror"), f"{dtype} r={r}")
+
+
+@pytest.mark.parametrize("name", ["disc48", "ellipse", "hexagon"])
+def test_lognormal_f32_footprints(mf, oracle_mod, name):
+    # float32 planes with +-1e6 outliers under the mirror boundary
+    mk = {"disc48": (lambda: mf.Footprint.disc(48), lambda: OF.disc(48)),
+          "ellipse": (lambda: mf.Footprint.ellipse(60, 20, 30), lambda: OF.ellipse(60, 20, 30)),
+          "hexagon": (lambda: mf.Footprint.regular_polygon(6, 40), lambda: OF.regular_polygon(6, 40))}
+    a, b = mk[name]
+    img = workloads.lognormal_f32(320, 180, planes=1, seed=2)[0]
+    got = run(mf, img, a(), "mirror")
+    assert_same(got, oracle_mod.filter(img, b(), "mirror"), name)
+
+
+@pytest.mark.parametrize("r", [8, 32, 100])
 def test_natural_u16_4096_sampled(mf, oracle_mod, r):
     img = workloads.natural_u16(4096, 4096, seed=1)
     got = run(mf, img, mf.Footprint.disc(r), "clamp")
