@@ -73,6 +73,64 @@ int mf_cnn_targets(const void* med, int w, int h, size_t stride_bytes, int dtype
 int mf_cnn_adam(float* p, float* m, float* v, const float* grad, int n, float lr, float b1,
                 float b2, float eps, int step, void* p_bf16, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * The network object and the learned filter.
+ *
+ * mf_learned holds the parameters (float32 master copy + bf16 copy, layout
+ * W1 b1 W2 b2 W3 b3 W4 b4 as above, mf_learned_param_count() floats), the
+ * Adam state and device workspaces sized on first use.  Create: He-normal
+ * weights from `seed`, output biases lo = 0, hi = 1 (an untrained network
+ * brackets the full range).  Workspace growth synchronizes the device.  One
+ * object must not be used from two streams at once.
+ * ------------------------------------------------------------------------ */
+typedef struct mf_learned mf_learned;
+
+int mf_learned_create(unsigned long long seed, mf_learned** out);
+void mf_learned_destroy(mf_learned* net);
+int mf_learned_param_count(void);
+/* Host float32 copies of all parameters (synchronous); set also resets the
+ * Adam state. */
+int mf_learned_get_params(const mf_learned* net, float* host);
+int mf_learned_set_params(mf_learned* net, const float* host);
+/* Bracket margin added on both sides, in units of the dtype's full range
+ * (calibrated on held-out images by the caller). */
+int mf_learned_set_margin(mf_learned* net, float margin);
+
+/* Forward pass over the cells of an 8-bit or 16-bit image: out_cells is
+ * f32 [ceil(h/8)][ceil(w/8)][16] (device), channel 0 = lo, 1 = hi. */
+int mf_learned_forward(mf_learned* net, const void* img, int w, int h, size_t stride_bytes,
+                       int dtype, int radius, float* out_cells, hipStream_t stream);
+
+/* One Adam step (learning rate lr) on the pinball loss (tau 0.02 for lo,
+ * 0.98 for hi) of the cell brackets against the min/max of `median` (the
+ * exact median image, same size/stride/dtype as img) over each cell.  If
+ * loss is not NULL it receives the mean loss (synchronous). */
+int mf_learned_train_step(mf_learned* net, const void* img, const void* median, int w, int h,
+                          size_t stride_bytes, int dtype, int radius, float lr, float* loss,
+                          hipStream_t stream);
+
+/* Tile grid the learned and bracketed filters use for this image. */
+int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
+                         int* tiles_y);
+
+/* Exact median filter of an 8/16-bit plane with caller-supplied per-tile
+ * value brackets: tile_brackets (device) holds (lo, hi) pairs of unsigned
+ * ints, tiles_x * tiles_y of them in row-major tile order.  Tiles whose
+ * medians fall outside their bracket are recomputed by the plain engine,
+ * so the output always equals median_filter's.  fallback_px (host, may be
+ * NULL; if set the call synchronizes) receives the number of output pixels
+ * in recomputed tiles.  `net` supplies workspace only. */
+int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                            const mf_footprint* fp, int boundary, const unsigned int* tile_brackets,
+                            mf_learned* net, void* out, unsigned long long* fallback_px,
+                            hipStream_t stream);
+
+/* Learned filter: the network proposes the brackets (union of a tile's
+ * cells, widened by the margin), then as median_filter_bracketed. */
+int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          const mf_footprint* fp, int boundary, mf_learned* net, void* out,
+                          unsigned long long* fallback_px, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,20 @@ def lib():
         "mf_cnn_targets": ([P, I, I, SZ, I, P, P], I),
         "mf_cnn_adam": ([P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, I, P, P], I),
+        "mf_learned_create": ([ctypes.c_ulonglong, PP], I),
+        "mf_learned_destroy": ([P], None),
+        "mf_learned_param_count": ([], I),
+        "mf_learned_get_params": ([P, P], I),
+        "mf_learned_set_params": ([P, P], I),
+        "mf_learned_set_margin": ([P, ctypes.c_float], I),
+        "mf_learned_forward": ([P, P, I, I, SZ, I, I, P, P], I),
+        "mf_learned_train_step": ([P, P, P, I, I, SZ, I, I, ctypes.c_float,
+                                   ctypes.POINTER(ctypes.c_float), P], I),
+        "mf_learned_tile_grid": ([I, I, I, P, IP, IP], I),
+        "median_filter_bracketed": ([P, I, I, SZ, I, P, I, P, P, P,
+                                     ctypes.POINTER(ctypes.c_ulonglong), P], I),
+        "median_filter_learned": ([P, I, I, SZ, I, P, I, P, P,
+                                   ctypes.POINTER(ctypes.c_ulonglong), P], I),
         "mf_tune_cache_save": ([ctypes.c_char_p], I),
     }
     for name, (args, res) in sig.items():
@@ -386,3 +400,92 @@ class cnn:
     def adam(p, m, v, grad, lr, step, p_bf16=None, b1=0.9, b2=0.999, eps=1e-8, stream=None):
         _check("mf_cnn_adam", lib().mf_cnn_adam(_p(p), _p(m), _p(v), _p(grad), p.numel(), lr, b1,
                                                 b2, eps, step, _p(p_bf16), _stream_ptr(stream)))
+
+
+class LearnedNet:
+    """The bracket-proposal network (parameters, Adam state, workspace)."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check("mf_learned_create", lib().mf_learned_create(int(seed), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def param_count():
+        return int(lib().mf_learned_param_count())
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.param_count(), dtype=np.float32)
+        _check("mf_learned_get_params", lib().mf_learned_get_params(self._h,
+                                                                    a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def set_params(self, a):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        assert a.size == self.param_count()
+        _check("mf_learned_set_params", lib().mf_learned_set_params(
+            self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_margin(self, margin: float):
+        _check("mf_learned_set_margin", lib().mf_learned_set_margin(self._h, float(margin)))
+
+    def forward(self, img, radius: int, out_cells=None, stream=None):
+        import torch
+        code, es, w, h, sb = _plane_args(img)
+        if out_cells is None:
+            out_cells = torch.empty(((h + 7) // 8, (w + 7) // 8, 16), dtype=torch.float32,
+                                    device=img.device)
+        _check("mf_learned_forward", lib().mf_learned_forward(
+            self._h, _p(img), w, h, sb, code, int(radius), _p(out_cells), _stream_ptr(stream)))
+        return out_cells
+
+    def train_step(self, img, median, radius: int, lr: float, stream=None):
+        code, es, w, h, sb = _plane_args(img)
+        loss = ctypes.c_float()
+        _check("mf_learned_train_step", lib().mf_learned_train_step(
+            self._h, _p(img), _p(median), w, h, sb, code, int(radius), float(lr),
+            ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def filter(self, img, fp: Footprint, boundary: str = "clamp", out=None, stream=None):
+        """Exact median via learned brackets; returns (out, fallback_pixels)."""
+        import torch
+        code, es, w, h, sb = _plane_args(img)
+        if out is None:
+            out = torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+        fb = ctypes.c_ulonglong()
+        _check("median_filter_learned", lib().median_filter_learned(
+            _p(img), w, h, sb, code, fp.handle, BOUNDARY[boundary], self._h, _p(out),
+            ctypes.byref(fb), _stream_ptr(stream)))
+        return out, fb.value
+
+    def filter_bracketed(self, img, fp: Footprint, brackets, boundary: str = "clamp", out=None,
+                         stream=None):
+        """Exact median with caller-supplied per-tile brackets (device uint32 [tiles][2])."""
+        import torch
+        code, es, w, h, sb = _plane_args(img)
+        if out is None:
+            out = torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+        fb = ctypes.c_ulonglong()
+        _check("median_filter_bracketed", lib().median_filter_bracketed(
+            _p(img), w, h, sb, code, fp.handle, BOUNDARY[boundary], _p(brackets), self._h,
+            _p(out), ctypes.byref(fb), _stream_ptr(stream)))
+        return out, fb.value
+
+    @staticmethod
+    def tile_grid(w: int, h: int, dtype: int, fp: Footprint):
+        tx, ty = ctypes.c_int(), ctypes.c_int()
+        _check("mf_learned_tile_grid", lib().mf_learned_tile_grid(w, h, dtype, fp.handle,
+                                                                  ctypes.byref(tx),
+                                                                  ctypes.byref(ty)))
+        return tx.value, ty.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.mf_learned_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

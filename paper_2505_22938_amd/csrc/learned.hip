@@ -1,0 +1,476 @@
+// Learned bracket proposal (not in the paper) around the exact engine.
+//
+// A four-layer 3x3 CNN on 8x8-pixel cells (input: cell mean and the radius
+// plane) predicts per cell a bracket [lo, hi] for the medians of the cell's
+// pixels.  A tile's bracket is the union over the cells it covers, widened
+// by a calibrated margin.  The bracketed tile kernel ranks only the box
+// pixels inside the bracket (exact counts, see tile_body's BR mode); a tile
+// where some median falls outside is flagged and recomputed by the plain
+// engine, so the output is always exact.  Training runs the network's own
+// forward, backward and Adam kernels (cnn.hip) on targets made from exact
+// median images.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "../../include/mf_cnn.h"
+#include "mf_internal.h"
+#include "tile_engine.h"
+
+namespace mf {
+
+// Parameter layout (floats): W1 b1 W2 b2 W3 b3 W4 b4; weights are
+// [cout][9][32], W4 has 16 output rows (0 = lo, 1 = hi, rest zero).
+constexpr int kW = 32 * 9 * 32, kW4 = 16 * 9 * 32;
+constexpr int kOffW[4] = {0, kW + 32, 2 * (kW + 32), 3 * (kW + 32)};
+constexpr int kOffB[4] = {kW, 2 * kW + 32, 3 * kW + 64, 3 * (kW + 32) + kW4};
+constexpr int kParams = 3 * (kW + 32) + kW4 + 16;
+
+template <int KT, int SHAPE, int IMAX>
+__global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  tile_body<KT, SHAPE, IMAX, false, true>(a, blockIdx.x, smem, nullptr);
+}
+
+template <int KT, int SHAPE, int IMAX>
+__global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc a,
+                                                               unsigned long long* fail_px) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tile = blockIdx.x;
+  if (a.tile_fail[tile] == 0) return;   // uniform per workgroup
+  tile_body<KT, SHAPE, IMAX, false, false>(a, tile, smem, nullptr);
+  if (threadIdx.x == 0) {
+    const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
+    const long long n = (long long)min(a.tw, a.w - tx0) * min(a.th, a.h - ty0);
+    atomicAdd(fail_px, (unsigned long long)n);
+  }
+}
+
+// Tile bracket = union of its cells' predicted brackets, widened by
+// `margin` (normalised units), in value keys clamped to [0, maxval].
+__global__ void bracket_kernel(const float* __restrict__ out, int hc, int wc, int tw, int th,
+                               int tiles_x, int ntiles, float maxval, float margin,
+                               uint2* __restrict__ br) {
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tile >= ntiles) return;
+  const int tx0 = (tile % tiles_x) * tw, ty0 = (tile / tiles_x) * th;
+  const int c0 = tx0 / 8, c1 = min(wc, (tx0 + tw + 7) / 8);
+  const int r0 = ty0 / 8, r1 = min(hc, (ty0 + th + 7) / 8);
+  float lo = 3.4e38f, hi = -3.4e38f;
+  for (int r = r0; r < r1; ++r)
+    for (int c = c0; c < c1; ++c) {
+      const float* o = out + ((long long)r * wc + c) * 16;
+      lo = fminf(lo, fminf(o[0], o[1]));
+      hi = fmaxf(hi, fmaxf(o[0], o[1]));
+    }
+  float L = floorf((lo - margin) * maxval), H = ceilf((hi + margin) * maxval);
+  L = fminf(fmaxf(L, 0.f), maxval);
+  H = fminf(fmaxf(H, 0.f), maxval);
+  if (!(L <= H)) {   // empty or NaN: no bracket
+    L = 0.f;
+    H = maxval;
+  }
+  br[tile] = make_uint2((unsigned)L, (unsigned)H);
+}
+
+}  // namespace mf
+
+struct mf_learned {
+  int dev = 0;
+  float* p = nullptr;        // master parameters
+  float* m = nullptr;
+  float* v = nullptr;
+  float* g = nullptr;
+  uint16_t* wbf = nullptr;   // bf16 copy, same element offsets as p
+  float margin = 0.0f;
+  int step = 0;
+  // cell workspace
+  long long cells_cap = 0;
+  int grid_w = 0, grid_h = 0;
+  uint16_t* act[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* out = nullptr;
+  float* tgt = nullptr;
+  uint16_t* dout = nullptr;
+  uint16_t* dbuf[2] = {nullptr, nullptr};
+  uint16_t* wflip = nullptr;
+  float* wsp = nullptr;
+  long long wsp_floats = 0;
+  float* loss_part = nullptr;
+  // tile workspace
+  long long tiles_cap = 0;
+  uint2* brackets = nullptr;
+  int* tile_fail = nullptr;
+  unsigned long long* fail_px = nullptr;
+};
+
+namespace {
+
+constexpr int kSegsPerBlock = 8;
+
+void free_cells(mf_learned* n) {
+  for (auto& a : n->act) (void)hipFree(a), a = nullptr;
+  (void)hipFree(n->out);
+  (void)hipFree(n->tgt);
+  (void)hipFree(n->dout);
+  (void)hipFree(n->dbuf[0]);
+  (void)hipFree(n->dbuf[1]);
+  (void)hipFree(n->wsp);
+  (void)hipFree(n->loss_part);
+  n->out = n->tgt = n->wsp = n->loss_part = nullptr;
+  n->dout = n->dbuf[0] = n->dbuf[1] = nullptr;
+  n->cells_cap = 0;
+}
+
+// Make sure the cell workspace fits an H x W cell grid.
+int ensure_cells(mf_learned* n, int H, int W) {
+  const long long cells = (long long)H * W;
+  const long long wsf = std::max(mf_cnn_wgrad_workspace(H, W, 32, kSegsPerBlock),
+                                 mf_cnn_wgrad_workspace(H, W, 16, kSegsPerBlock));
+  if (cells <= n->cells_cap && wsf <= n->wsp_floats) {
+    n->grid_w = W;
+    n->grid_h = H;
+    return MF_OK;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return MF_ERR_HIP;
+  free_cells(n);
+  bool ok = true;
+  for (auto& a : n->act) ok = ok && hipMalloc(&a, cells * 32 * 2) == hipSuccess;
+  ok = ok && hipMalloc(&n->out, cells * 16 * 4) == hipSuccess;
+  ok = ok && hipMalloc(&n->tgt, cells * 2 * 4) == hipSuccess;
+  ok = ok && hipMalloc(&n->dout, cells * 32 * 2) == hipSuccess;
+  ok = ok && hipMalloc(&n->dbuf[0], cells * 32 * 2) == hipSuccess;
+  ok = ok && hipMalloc(&n->dbuf[1], cells * 32 * 2) == hipSuccess;
+  ok = ok && hipMalloc(&n->wsp, wsf * 4) == hipSuccess;
+  ok = ok && hipMalloc(&n->loss_part, ((cells + 255) / 256) * 4) == hipSuccess;
+  if (!ok) {
+    free_cells(n);
+    return MF_ERR_NOMEM;
+  }
+  n->cells_cap = cells;
+  n->wsp_floats = wsf;
+  n->grid_w = W;
+  n->grid_h = H;
+  return MF_OK;
+}
+
+int ensure_tiles(mf_learned* n, long long tiles) {
+  if (tiles <= n->tiles_cap) return MF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return MF_ERR_HIP;
+  (void)hipFree(n->brackets);
+  (void)hipFree(n->tile_fail);
+  n->brackets = nullptr;
+  n->tile_fail = nullptr;
+  n->tiles_cap = 0;
+  if (hipMalloc(&n->brackets, tiles * sizeof(uint2)) != hipSuccess ||
+      hipMalloc(&n->tile_fail, tiles * sizeof(int)) != hipSuccess)
+    return MF_ERR_NOMEM;
+  n->tiles_cap = tiles;
+  return MF_OK;
+}
+
+int footprint_radius(const mf_footprint* fp) {
+  return std::max(std::max(-fp->dx_min, fp->dx_max), std::max(-fp->dy_min, fp->dy_max));
+}
+
+// Forward pass over the cells of an image; results in n->out.
+int net_forward(mf_learned* n, const void* img, int w, int h, size_t stride, int dtype,
+                int radius, hipStream_t s) {
+  const int H = (h + 7) / 8, W = (w + 7) / 8;
+  int rc = ensure_cells(n, H, W);
+  if (rc) return rc;
+  if ((rc = mf_cnn_features(img, w, h, stride, dtype, radius, n->act[0], s))) return rc;
+  for (int l = 0; l < 3; ++l)
+    if ((rc = mf_cnn_conv_forward(n->act[l], H, W, n->wbf + mf::kOffW[l], n->p + mf::kOffB[l], 32,
+                                  0, nullptr, n->act[l + 1], s)))
+      return rc;
+  return mf_cnn_conv_forward(n->act[3], H, W, n->wbf + mf::kOffW[3], n->p + mf::kOffB[3], 16, 1,
+                             nullptr, n->out, s);
+}
+
+using BrKernel = void (*)(mf::ImageDesc);
+using FbKernel = void (*)(mf::ImageDesc, unsigned long long*);
+
+template <int KT, int SHAPE>
+void pick(int imax, BrKernel* b, FbKernel* f) {
+  switch (imax) {
+    case 9: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 9>; *f = mf::mf_fallback_kernel<KT, SHAPE, 9>; break;
+    case 17: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 17>; *f = mf::mf_fallback_kernel<KT, SHAPE, 17>; break;
+    case 25: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 25>; *f = mf::mf_fallback_kernel<KT, SHAPE, 25>; break;
+    default: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 33>; *f = mf::mf_fallback_kernel<KT, SHAPE, 33>; break;
+  }
+}
+
+// Bracketed filter with per-tile brackets already in n->brackets (or the
+// caller's device array `br`), then the plain pass over flagged tiles.
+int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int h,
+                     size_t stride, int dtype, const mf_footprint* fp, int boundary, void* out,
+                     unsigned long long* fallback_px, hipStream_t s, const mf::ImageDesc& plan) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MF_ERR_HIP;
+  const void* table = nullptr;
+  int rc = mf::footprint_device_table(fp, dev, &table);
+  if (rc) return rc;
+  mf::ImageDesc a = plan;
+  mf::bind_image(&a, img, w, h, stride, dtype, fp, boundary, (fp->taps - 1) / 2, table);
+  a.out = out;
+  a.brackets = br;
+  a.tile_fail = n->tile_fail;
+  const long long ntiles = (long long)a.tiles_x * a.tiles_y;
+  if (hipMemsetAsync(n->tile_fail, 0, ntiles * sizeof(int), s) != hipSuccess ||
+      hipMemsetAsync(n->fail_px, 0, sizeof(unsigned long long), s) != hipSuccess)
+    return MF_ERR_HIP;
+  BrKernel bk = nullptr;
+  FbKernel fk = nullptr;
+  if (dtype == MF_U8) {
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U8, mf::SHAPE_DISC>(a.imax, &bk, &fk);
+    else pick<mf::KEY_U8, mf::SHAPE_SPANS>(a.imax, &bk, &fk);
+  } else {
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(a.imax, &bk, &fk);
+    else pick<mf::KEY_U16, mf::SHAPE_SPANS>(a.imax, &bk, &fk);
+  }
+  (void)hipFuncSetAttribute((const void*)bk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            a.lds_bytes);
+  (void)hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            a.lds_bytes);
+  hipLaunchKernelGGL(bk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a);
+  hipLaunchKernelGGL(fk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a,
+                     n->fail_px);
+  if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
+  if (fallback_px) {
+    if (hipMemcpyAsync(fallback_px, n->fail_px, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return MF_ERR_HIP;
+  }
+  return MF_OK;
+}
+
+int learned_plan(int dtype, const mf_footprint* fp, mf::ImageDesc* plan) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MF_ERR_HIP;
+  mf::DeviceInfo di;
+  int rc = mf::device_info(dev, &di);
+  if (rc) return rc;
+  if ((rc = mf::choose_plan(dtype, fp, di.lds_max, 33, plan))) return rc;
+  if (plan->gs || plan->T > 65534) return MF_ERR_UNSUPPORTED;
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mf_learned_param_count(void) { return mf::kParams; }
+
+void mf_learned_destroy(mf_learned* n) {
+  if (!n) return;
+  (void)hipDeviceSynchronize();
+  free_cells(n);
+  (void)hipFree(n->p);
+  (void)hipFree(n->m);
+  (void)hipFree(n->v);
+  (void)hipFree(n->g);
+  (void)hipFree(n->wbf);
+  (void)hipFree(n->wflip);
+  (void)hipFree(n->brackets);
+  (void)hipFree(n->tile_fail);
+  (void)hipFree(n->fail_px);
+  delete n;
+}
+
+int mf_learned_set_params(mf_learned* n, const float* host) {
+  if (!n || !host) return MF_ERR_INVALID_ARG;
+  std::vector<uint16_t> bf(mf::kParams);
+  for (int i = 0; i < mf::kParams; ++i) {
+    uint32_t u;
+    std::memcpy(&u, &host[i], 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    bf[i] = (uint16_t)(u >> 16);
+  }
+  if (hipMemcpy(n->p, host, mf::kParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(n->wbf, bf.data(), mf::kParams * 2, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(n->m, 0, mf::kParams * 4) != hipSuccess ||
+      hipMemset(n->v, 0, mf::kParams * 4) != hipSuccess)
+    return MF_ERR_HIP;
+  n->step = 0;
+  return MF_OK;
+}
+
+int mf_learned_get_params(const mf_learned* n, float* host) {
+  if (!n || !host) return MF_ERR_INVALID_ARG;
+  return hipMemcpy(host, n->p, mf::kParams * 4, hipMemcpyDeviceToHost) == hipSuccess ? MF_OK
+                                                                                      : MF_ERR_HIP;
+}
+
+int mf_learned_create(unsigned long long seed, mf_learned** out) {
+  if (!out) return MF_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto* n = new (std::nothrow) mf_learned;
+  if (!n) return MF_ERR_NOMEM;
+  if (hipGetDevice(&n->dev) != hipSuccess) {
+    delete n;
+    return MF_ERR_HIP;
+  }
+  if (hipMalloc(&n->p, mf::kParams * 4) != hipSuccess ||
+      hipMalloc(&n->m, mf::kParams * 4) != hipSuccess ||
+      hipMalloc(&n->v, mf::kParams * 4) != hipSuccess ||
+      hipMalloc(&n->g, mf::kParams * 4) != hipSuccess ||
+      hipMalloc(&n->wbf, mf::kParams * 2) != hipSuccess ||
+      hipMalloc(&n->wflip, 32 * 9 * 32 * 2) != hipSuccess ||
+      hipMalloc(&n->fail_px, sizeof(unsigned long long)) != hipSuccess) {
+    mf_learned_destroy(n);
+    return MF_ERR_NOMEM;
+  }
+  // He-normal weights over the real fan-in (layer 1 sees 2 input channels),
+  // zero biases except the output layer, which starts at the full range
+  // (lo = 0, hi = 1) so an untrained net brackets everything.
+  std::mt19937_64 rng(seed);
+  std::vector<float> h(mf::kParams, 0.0f);
+  for (int l = 0; l < 4; ++l) {
+    const int cout = l == 3 ? 2 : 32, cin = l == 0 ? 2 : 32;
+    std::normal_distribution<float> nd(0.0f, std::sqrt(2.0f / (9.0f * cin)) * (l == 3 ? 0.1f : 1.0f));
+    for (int co = 0; co < cout; ++co)
+      for (int t = 0; t < 9; ++t)
+        for (int ci = 0; ci < cin; ++ci) h[mf::kOffW[l] + (co * 9 + t) * 32 + ci] = nd(rng);
+  }
+  h[mf::kOffB[3]] = 0.0f;
+  h[mf::kOffB[3] + 1] = 1.0f;
+  const int rc = mf_learned_set_params(n, h.data());
+  if (rc) {
+    mf_learned_destroy(n);
+    return rc;
+  }
+  *out = n;
+  return MF_OK;
+}
+
+int mf_learned_set_margin(mf_learned* n, float margin) {
+  if (!n || !(margin >= 0.0f)) return MF_ERR_INVALID_ARG;
+  n->margin = margin;
+  return MF_OK;
+}
+
+int mf_learned_forward(mf_learned* n, const void* img, int w, int h, size_t stride_bytes,
+                       int dtype, int radius, float* out_cells, hipStream_t s) {
+  if (!n || !img || !out_cells || w <= 0 || h <= 0 || radius < 0 ||
+      (dtype != MF_U8 && dtype != MF_U16))
+    return MF_ERR_INVALID_ARG;
+  int rc = net_forward(n, img, w, h, stride_bytes, dtype, radius, s);
+  if (rc) return rc;
+  const long long cells = (long long)((w + 7) / 8) * ((h + 7) / 8);
+  return hipMemcpyAsync(out_cells, n->out, cells * 16 * 4, hipMemcpyDeviceToDevice, s) ==
+                 hipSuccess
+             ? MF_OK
+             : MF_ERR_HIP;
+}
+
+int mf_learned_train_step(mf_learned* n, const void* img, const void* median, int w, int h,
+                          size_t stride_bytes, int dtype, int radius, float lr, float* loss,
+                          hipStream_t s) {
+  if (!n || !img || !median || w <= 0 || h <= 0 || !(lr > 0) ||
+      (dtype != MF_U8 && dtype != MF_U16))
+    return MF_ERR_INVALID_ARG;
+  int rc = net_forward(n, img, w, h, stride_bytes, dtype, radius, s);
+  if (rc) return rc;
+  const int H = n->grid_h, W = n->grid_w;
+  const int cells = H * W;
+  if ((rc = mf_cnn_targets(median, w, h, stride_bytes, dtype, n->tgt, s))) return rc;
+  if ((rc = mf_cnn_pinball(n->out, 16, n->tgt, cells, 0.02f, 0.98f, n->dout, n->loss_part, s)))
+    return rc;
+  // backward through the four layers
+  const uint16_t* dcur = n->dout;
+  for (int l = 3; l >= 0; --l) {
+    const int cout = l == 3 ? 16 : 32;
+    if ((rc = mf_cnn_conv_wgrad(n->act[l], dcur, H, W, cout, kSegsPerBlock, n->wsp,
+                                n->g + mf::kOffW[l], n->g + mf::kOffB[l], s)))
+      return rc;
+    if (l == 0) break;
+    uint16_t* dnext = n->dbuf[l & 1];
+    if ((rc = mf_cnn_flip_weights(n->wbf + mf::kOffW[l], cout, n->wflip, s)) ||
+        (rc = mf_cnn_conv_forward(dcur, H, W, n->wflip, nullptr, 32, 2, n->act[l], dnext, s)))
+      return rc;
+    dcur = dnext;
+  }
+  // zero the gradients of the unused output rows and input channels
+  (void)hipMemsetAsync(n->g + mf::kOffW[3] + 2 * 9 * 32, 0, (16 - 2) * 9 * 32 * 4, s);
+  (void)hipMemsetAsync(n->g + mf::kOffB[3] + 2, 0, 14 * 4, s);
+  n->step += 1;
+  if ((rc = mf_cnn_adam(n->p, n->m, n->v, n->g, mf::kParams, lr, 0.9f, 0.999f, 1e-8f, n->step,
+                        n->wbf, s)))
+    return rc;
+  if (loss) {
+    std::vector<float> part((cells + 255) / 256);
+    if (hipMemcpyAsync(part.data(), n->loss_part, part.size() * 4, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return MF_ERR_HIP;
+    double sum = 0;
+    for (float f : part) sum += f;
+    *loss = (float)(sum / cells);
+  }
+  return MF_OK;
+}
+
+int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                            const mf_footprint* fp, int boundary, const unsigned int* tile_brackets,
+                            mf_learned* net, void* out, unsigned long long* fallback_px,
+                            hipStream_t stream) {
+  int rc = mf::validate_image(img, w, h, stride_bytes, dtype, fp, boundary, out);
+  if (rc) return rc;
+  if (!net || !tile_brackets || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
+  if (w == 0 || h == 0) {
+    if (fallback_px) *fallback_px = 0;
+    return MF_OK;
+  }
+  mf::ImageDesc plan{};
+  if ((rc = learned_plan(dtype, fp, &plan))) return rc;
+  const long long ntiles = (long long)((w + plan.tw - 1) / plan.tw) * ((h + plan.th - 1) / plan.th);
+  if ((rc = ensure_tiles(net, ntiles))) return rc;
+  return bracketed_filter(net, reinterpret_cast<const uint2*>(tile_brackets), img, w, h,
+                          stride_bytes, dtype, fp, boundary, out, fallback_px, stream, plan);
+}
+
+int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          const mf_footprint* fp, int boundary, mf_learned* net, void* out,
+                          unsigned long long* fallback_px, hipStream_t stream) {
+  int rc = mf::validate_image(img, w, h, stride_bytes, dtype, fp, boundary, out);
+  if (rc) return rc;
+  if (!net || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
+  if (w == 0 || h == 0) {
+    if (fallback_px) *fallback_px = 0;
+    return MF_OK;
+  }
+  mf::ImageDesc plan{};
+  if ((rc = learned_plan(dtype, fp, &plan))) return rc;
+  const int tiles_x = (w + plan.tw - 1) / plan.tw, tiles_y = (h + plan.th - 1) / plan.th;
+  const long long ntiles = (long long)tiles_x * tiles_y;
+  if ((rc = ensure_tiles(net, ntiles))) return rc;
+  if ((rc = net_forward(net, img, w, h, stride_bytes, dtype, footprint_radius(fp), stream)))
+    return rc;
+  const float maxval = dtype == MF_U8 ? 255.0f : 65535.0f;
+  hipLaunchKernelGGL(mf::bracket_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
+                     stream, net->out, net->grid_h, net->grid_w, plan.tw, plan.th, tiles_x,
+                     (int)ntiles, maxval, net->margin, net->brackets);
+  if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
+  return bracketed_filter(net, net->brackets, img, w, h, stride_bytes, dtype, fp, boundary, out,
+                          fallback_px, stream, plan);
+}
+
+int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
+                         int* tiles_y) {
+  if (!fp || w <= 0 || h <= 0 || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
+  mf::ImageDesc plan{};
+  const int rc = learned_plan(dtype, fp, &plan);
+  if (rc) return rc;
+  if (tiles_x) *tiles_x = (w + plan.tw - 1) / plan.tw;
+  if (tiles_y) *tiles_y = (h + plan.th - 1) / plan.th;
+  return MF_OK;
+}
+
+}  // extern "C"

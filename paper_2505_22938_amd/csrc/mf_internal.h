@@ -62,6 +62,9 @@ struct ImageDesc {
   // kernel selection: key type, shape, 1 = global-scratch variant, and the
   // register capacity (elements per thread) of the LDS variant
   int kt, shape, gs, imax;
+  // bracketed tiles (learned path): per-tile [lo, hi] keys and fail flags
+  const uint2* brackets;
+  int* tile_fail;
 };
 
 struct DeviceInfo {

@@ -66,7 +66,7 @@ int band_geometry(const mf_footprint* fp, int tw, int th, ImageDesc* d) {
 
 int table_bytes(const ImageDesc* d) {
   const int nr4 = round_up(d->nrows, 4);
-  return 64 + 4 * nr4 + 8 * nr4 + 16 * d->ncols;
+  return 128 + 4 * nr4 + 8 * nr4 + 16 * d->ncols;   // scan words, spans, offsets
 }
 
 }  // namespace
@@ -105,7 +105,7 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   // (float keys).  Region B: digit counts during the sort, afterwards the
   // ordinal image and the per-wave seed histograms.
   const int TP = round_up(T, 8) + 16;
-  const int kb = dtype == MF_F32 ? 4 * round_up(T, 4) : 4 * TP;
+  const int kb = dtype == MF_F32 ? 4 * (round_up(T, 4) + 4) : 4 * TP;
   const int pb = dtype == MF_F32 ? 2 * TP : 0;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
   const int hb = kWaves * 128 * 4;
@@ -217,6 +217,8 @@ void bind_image(ImageDesc* d, const void* img, int w, int h, size_t stride_bytes
   d->spans = static_cast<const short2*>(spans);
   d->counters = nullptr;
   d->scratch = nullptr;
+  d->brackets = nullptr;
+  d->tile_fail = nullptr;
 }
 
 int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype,

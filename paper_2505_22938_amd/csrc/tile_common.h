@@ -69,14 +69,17 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // for the first pass); elements numbered >= T are absent.  ITEMS is odd and
 // ITEMS * kThreads >= T.
 //
-// Output: with PAYLOAD (float keys) the sorted keys go to kbuf and the
-// payload to pbuf.  Without PAYLOAD the element is one word key << 16 | loc;
-// the last pass splits it into loc -> omega[dst] and key -> crev[dst].
+// Output: with PAYLOAD (float keys) the last pass writes the sorted keys to
+// kout[dst] and the payload to omega[dst].  Without PAYLOAD the element is
+// one word key << 16 | loc; the last pass splits it into loc -> omega[dst]
+// and key -> crev[dst].  kbuf/pbuf are the exchange buffers of earlier
+// passes; the output arrays may alias them (the last pass reads only
+// registers).
 template <int ITEMS, bool PAYLOAD>
 __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
                                                  int T, int shift0, int passes,
                                                  uint32_t* kbuf, uint16_t* pbuf,
-                                                 uint16_t* omega, uint16_t* crev,
+                                                 uint16_t* omega, uint16_t* crev, uint32_t* kout,
                                                  uint16_t* cnt, uint32_t* wsum) {
   const int t = threadIdx.x;
   for (int pass = 0; pass < passes; ++pass) {
@@ -134,8 +137,13 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
         const uint32_t d = (key[i] >> sh) & 15u;
         const uint32_t dst = (uint32_t)cnt[d * kThreads + t] + ((lr[i >> 2] >> ((i & 3) * 8)) & 0xffu);
         if (PAYLOAD) {
-          kbuf[dst] = key[i];
-          pbuf[dst] = pos[i];
+          if (pass + 1 < passes) {
+            kbuf[dst] = key[i];
+            pbuf[dst] = pos[i];
+          } else {
+            kout[dst] = key[i];
+            omega[dst] = pos[i];
+          }
         } else if (pass + 1 < passes) {
           kbuf[dst] = key[i];
         } else {

@@ -90,19 +90,22 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
 // this lane's entries of the first block above p ([p, p+64)) and below p
 // ([p-64, p)), loaded by the caller (only the one for the taken direction
 // is used).
+// T bounds the valid ordinals ([0, T) here; entries beyond are padding).
+// Returns -1 if no member of rank k exists among the valid ordinals (only
+// possible when some pixels are outside the omnigram, see BR below).
 template <int SHAPE>
-__device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, const ImageDesc& a,
-                                         const uint16_t* om, const short2* rsp, int& blocks,
-                                         uint32_t pre_up, uint32_t pre_dn) {
+__device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int T,
+                                         const ImageDesc& a, const uint16_t* om,
+                                         const short2* rsp, int& blocks, uint32_t pre_up,
+                                         uint32_t pre_dn) {
   const int lane = threadIdx.x & 63;
-  const int T = a.T;
   const int cap = (T >> 6) + 2;
   if (c <= k) {
     int need = k - c;
     int b = p;
     uint32_t cur = pre_up;
     for (int it = 0; it < cap; ++it, b += 64) {
-      const uint32_t nxt = om[min(b + 64 + lane, T - 1)];
+      const uint32_t nxt = om[min(max(b + 64 + lane, 0), T - 1)];
       const bool in = b + lane < T &&
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
       const uint64_t mask = __ballot(in);
@@ -140,18 +143,18 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, cons
       cur = nxt;
     }
   }
-  return -1;  // unreachable for a consistent omnigram
+  return -1;
 }
 
 template <int KT, int SHAPE>
-__device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
+__device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, int T,
                                            const ImageDesc& a, const uint16_t* om,
                                            const short2* rsp, int& blocks) {
   const int lane = threadIdx.x & 63;
   const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
   const bool up = c <= k;
-  const uint32_t pre = up ? om[min(p + lane, a.T - 1)] : om[max(p - 64 + lane, 0)];
-  return scan_core<SHAPE>(p, c, k, cxy, a, om, rsp, blocks, pre, pre);
+  const uint32_t pre = up ? om[min(max(p + lane, 0), T - 1)] : om[max(p - 64 + lane, 0)];
+  return scan_core<SHAPE>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre);
 }
 
 // Lane-parallel rank selection: every lane refines its own window.  Same
@@ -164,7 +167,7 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy,
 // test.  After `budget` groups an unfinished lane returns -1 with (p, c) set
 // to its frontier, for a wave-cooperative finish.
 template <int SHAPE>
-__device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget,
+__device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget, int T,
                                            const ImageDesc& a, const uint16_t* om,
                                            const short2* rsp, int& groups) {
   const bool up = c <= k;
@@ -180,7 +183,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
     uint32_t bits = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const bool in_range = up ? (q + j >= p) : (q + j < p);
+      const bool in_range = up ? (q + j >= p && q + j < T) : (q + j < p);
       bits |= (uint32_t)(in_range &&
                          member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp)) << j;
     }
@@ -204,7 +207,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
     }
   }
   // full groups: count members only
-  while (m < 0 && (up ? q < a.T : q >= 0) && it < budget) {
+  while (m < 0 && (up ? q < T : q >= 0) && it < budget) {
     const uint4 g = *reinterpret_cast<const uint4*>(om + q);
     const uint32_t e[8] = {g.x, g.x >> 16, g.y, g.y >> 16, g.z, g.z >> 16, g.w, g.w >> 16};
     int cnt = 0;
@@ -237,7 +240,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
   if (m < 0) {
     p = up ? q : q + 8;
     if (p < 0) p = 0;
-    if (p > a.T) p = a.T;
+    if (p > T) p = T;
     c = below;
   }
   return m;
@@ -245,12 +248,17 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 
 // Seed solve for the window centred at box (cx, cy): histogram of its
 // ordinals >> hist_shift, pick the bin holding rank k, refine by scanning.
-template <int KT, int SHAPE>
-__device__ __forceinline__ int seed_solve(int cx, int cy, const ImageDesc& a,
+// BR (bracketed tiles): ordinal 0 stands for every pixel below the bracket
+// and 0xffff for every pixel above it; the top histogram bin absorbs the
+// latter, and a pivot in bin 0 starts at ordinal 1 with the exact count of
+// below-bracket pixels in the window.
+template <int KT, int SHAPE, bool BR>
+__device__ __forceinline__ int seed_solve(int cx, int cy, int T, const ImageDesc& a,
                                           const uint16_t* om, const uint16_t* I, uint32_t* hist,
                                           const short2* rsp, int& blocks) {
   const int lane = threadIdx.x & 63;
   const int k = a.rank;
+  int zeros = 0;
   // 256 bins of 16-bit counts, two per word (a window has < 65536 taps)
   hist[lane * 2] = 0;
   hist[lane * 2 + 1] = 0;
@@ -259,7 +267,12 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, const ImageDesc& a,
     const short2 s = rsp[i];
     const int row = (cy + a.dy_min + i) * a.pitch + cx;
     for (int x = s.x; x <= s.y; ++x) {
-      const uint32_t b = (uint32_t)I[row + x] >> a.hist_shift;
+      const uint32_t iv = I[row + x];
+      uint32_t b = iv >> a.hist_shift;
+      if (BR) {
+        b = min(b, 255u);
+        zeros += iv == 0;
+      }
       atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
     }
   }
@@ -281,8 +294,15 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, const ImageDesc& a,
   const uint64_t who = __ballot(bin >= 0);
   const int src = __ffsll((unsigned long long)who) - 1;
   const int sbin = __builtin_amdgcn_readlane(bin, src);
-  const int sbase = __builtin_amdgcn_readlane((int)base, src);
-  return scan_select<KT, SHAPE>(sbin << a.hist_shift, sbase, k, cx, cy, a, om, rsp, blocks);
+  int sbase = __builtin_amdgcn_readlane((int)base, src);
+  int p = sbin << a.hist_shift;
+  if (BR && p == 0) {
+    // ordinal 1 with the window's below-bracket count
+    for (int d = 32; d >= 1; d >>= 1) zeros += __shfl_xor(zeros, d, 64);
+    p = 1;
+    sbase = zeros;
+  }
+  return scan_select<KT, SHAPE>(p, sbase, k, cx, cy, T, a, om, rsp, blocks);
 }
 
 // Count change when the window centred at box (cx, cy) moves right by one
@@ -313,14 +333,15 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDes
   return delta;
 }
 
-// Reverse map (paper, "Method Summary" step 7): the output is C[m].
+// Reverse map (paper, "Method Summary" step 7): the output is C[m].  For
+// bracketed tiles the stored key is relative to the bracket's low end lo.
 template <int KT>
 __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, const uint32_t* kbuf,
-                                          const uint16_t* crev, int m) {
+                                          const uint16_t* crev, int m, uint32_t lo) {
   const long long o = (long long)gy * a.stride + gx;
-  if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)crev[m];
-  if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = crev[m];
-  if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m]);
+  if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)(crev[m] + lo);
+  if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = (uint16_t)(crev[m] + lo);
+  if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m] + lo);
 }
 
 // One output tile.  All threads of the workgroup must call it.
@@ -328,9 +349,16 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 // GS = true: they live in the workgroup's global scratch slot `gslot`
 // (boxes too large for LDS); the ordinal image, histograms and footprint
 // tables stay in LDS.
-template <int KT, int SHAPE, int IMAX, bool GS>
+// BR = true (LDS variant only): the tile has a value bracket [lo, hi]
+// (a.brackets[tile], keys).  Only box pixels inside it are sorted; they take
+// ordinals 1..Tc, pixels below take ordinal 0 and pixels above 0xffff in the
+// ordinal image, so every count stays exact.  A window whose median is
+// outside the bracket cannot find a member of rank k among ordinals 1..Tc;
+// the tile is then flagged in a.tile_fail and left for the plain pass.
+template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false>
 __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned char* smem,
                                           unsigned char* gslot) {
+  static_assert(!(GS && BR), "bracketed tiles use the LDS variant");
   const int T = a.T;
   unsigned char* abase = GS ? gslot : smem;   // region holding the sorted arrays
   uint32_t* kbuf = reinterpret_cast<uint32_t*>(abase);                // sort exchange / f32 C
@@ -342,15 +370,23 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   uint32_t* hist_all = reinterpret_cast<uint32_t*>(smem + a.off_hist);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + a.off_tab);
   const int nr4 = (a.nrows + 3) & ~3;
-  short2* rsp = reinterpret_cast<short2*>(smem + a.off_tab + 64);
-  int2* hrow = reinterpret_cast<int2*>(smem + a.off_tab + 64 + 4 * nr4);
-  int4* vtab = reinterpret_cast<int4*>(smem + a.off_tab + 64 + 12 * nr4);
+  short2* rsp = reinterpret_cast<short2*>(smem + a.off_tab + 128);   // after wsum (32 words)
+  int2* hrow = reinterpret_cast<int2*>(smem + a.off_tab + 128 + 4 * nr4);
+  int4* vtab = reinterpret_cast<int4*>(smem + a.off_tab + 128 + 12 * nr4);
 
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
   const long long clk0 = a.counters ? (long long)clock64() : 0;
   const int gx0 = tx0 + a.dx_min, gy0 = ty0 + a.dy_min;
+  uint32_t blo = 0, bhi = 0xffffffffu;   // bracket (keys)
+  if (BR) {
+    const uint2 b = a.brackets[tile];
+    blo = b.x;
+    bhi = b.y;
+  }
+  int Tv = T;        // ordinals [0, Tv) are valid omnigram entries
+  int mlo = 0;       // smallest ordinal a member may have
 
   // footprint tables: row spans, per-row horizontal offsets, per-column
   // vertical offsets (down: entering, leaving; up: entering, leaving)
@@ -367,6 +403,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
                         (s.x - 1) * a.pitch + dx, s.y * a.pitch + dx);
   }
 
+  uint64_t below_bits = 0, above_bits = 0;   // BR: classes of this thread's striped items
   if constexpr (!GS) {
     // 1. load the box (striped order)
     uint32_t key[IMAX];
@@ -374,7 +411,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     {
       int lx = t % a.bw, ly = t / a.bw;
       const int sx = kThreads % a.bw, sy = kThreads / a.bw;
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < IMAX; ++i) {
         const int e = i * kThreads + t;
         uint32_t kk = 0, q = 0;
@@ -401,13 +438,67 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
       }
     }
 
-    // 2. ordinal transform
-    if (KT == KEY_U8)
-      block_radix_sort<IMAX, false>(key, pos, T, 16, 2, kbuf, pbuf, om, crev, cnt, wsum);
-    else if (KT == KEY_U16)
-      block_radix_sort<IMAX, false>(key, pos, T, 16, 4, kbuf, pbuf, om, crev, cnt, wsum);
+    int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
+    int Ts = T;   // elements sorted
+    if constexpr (BR) {
+      // keep the pixels inside the bracket, keyed relative to its low end
+      int ncand = 0;
+#pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = i * kThreads + t;
+        const uint32_t kv = KT == KEY_F32 ? key[i] : key[i] >> 16;
+        const bool valid = e < T;
+        const bool below = valid && kv < blo, above = valid && kv > bhi;
+        below_bits |= (uint64_t)below << i;
+        above_bits |= (uint64_t)above << i;
+        ncand += valid && !below && !above;
+      }
+      const uint32_t base = block_exclusive_scan((uint32_t)ncand, wsum);
+      if (t == kThreads - 1) wsum[kWaves] = base + ncand;
+      int o = (int)base;
+#pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = i * kThreads + t;
+        if (e < T && !((below_bits >> i) & 1) && !((above_bits >> i) & 1)) {
+          if (KT == KEY_F32) {
+            kbuf[o] = key[i] - blo;
+            pbuf[o] = pos[i];
+          } else {
+            kbuf[o] = key[i] - (blo << 16);
+          }
+          ++o;
+        }
+      }
+      __syncthreads();
+      Ts = (int)wsum[kWaves];
+#pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = i * kThreads + t;
+        uint32_t kk = 0;
+        uint16_t q = 0;
+        if (e < Ts) {
+          kk = kbuf[e];
+          if (KT == KEY_F32) q = pbuf[e];
+        }
+        key[i] = kk;
+        pos[i] = q;
+      }
+      // passes: 4-bit digits covering hi - lo
+      const uint32_t span = bhi - blo;
+      passes = 1;
+      while (passes < (KT == KEY_F32 ? 8 : 4) && (span >> (4 * passes)) != 0) ++passes;
+      Tv = Ts + 1;
+      mlo = 1;
+    }
+
+    // 2. ordinal transform (BR: ordinals shifted by one)
+    const int sh = KT == KEY_F32 ? 0 : 16;
+    if (KT == KEY_F32)
+      block_radix_sort<IMAX, true>(key, pos, Ts, sh, passes, kbuf, pbuf, om + mlo, nullptr,
+                                   kbuf + mlo, cnt, wsum);
     else
-      block_radix_sort<IMAX, true>(key, pos, T, 0, 8, kbuf, pbuf, om, crev, cnt, wsum);
+      block_radix_sort<IMAX, false>(key, pos, Ts, sh, passes, kbuf, pbuf, om + mlo, crev + mlo,
+                                    nullptr, cnt, wsum);
   } else {
     // load the box straight into global scratch as 64-bit words
     uint64_t* x0 = reinterpret_cast<uint64_t*>(gslot);
@@ -429,11 +520,25 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
                       wsum);
   }
   // omnigram padding: locations outside the box (box width < 256)
-  if (t < 16) om[T + t] = 0xffff;
+  if (t < 16) om[Tv + t] = 0xffff;
+  if (BR && t == 16) om[0] = 0xffff;
   // 3. ordinal image (overwrites the sort's count table)
-  for (int v = t; v < T; v += kThreads) {
+  for (int v = mlo + t; v < Tv; v += kThreads) {
     const uint32_t loc = (uint32_t)om[v];
     I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
+  }
+  if (BR) {
+    // pixels outside the bracket: striped item i of this thread is box
+    // element i * kThreads + t
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i) {
+      const bool bl = (below_bits >> i) & 1, ab = (above_bits >> i) & 1;
+      if (bl || ab) {
+        const int e = i * kThreads + t;
+        const int ly = e / a.bw, lx = e - ly * a.bw;
+        I[ly * a.pitch + lx] = bl ? (uint16_t)0 : (uint16_t)0xffff;
+      }
+    }
   }
   __syncthreads();
   const long long clk1 = a.counters ? (long long)clock64() : 0;
@@ -448,33 +553,51 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   const int row0 = band * R;                 // first output row of this lane's band
   const int cxl = col - a.dx_min;            // lane's window centre, box coords
   int m = 0;
+  bool failed = false;                       // BR: a median fell outside the bracket
 
-  // 4a. seed + first row of each band, one segment at a time
-  for (int s = 0; s < segs; ++s) {
-    const int cy = (wid * segs + s) * R - a.dy_min;
-    int ms = seed_solve<KT, SHAPE>(0 - a.dx_min, cy, a, om, I, hist, rsp, blocks);
+  // 4a. seed + first row of each band, one segment at a time.  Windows
+  // outside the image are not computed: bands starting below it are
+  // skipped and the walk stops at the last column inside it.
+  const int cols_in = min(tw, a.w - tx0);
+  for (int s = 0; s < segs && !failed; ++s) {
+    const int brow = (wid * segs + s) * R;
+    if (ty0 + brow >= a.h) break;
+    const int cy = brow - a.dy_min;
+    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, a, om, I, hist, rsp, blocks);
     ++seeds;
+    if (BR && ms < mlo) {
+      failed = true;
+      break;
+    }
     m = set_lane(ms, s * tw, m);
-    for (int c = 1; c < tw; ++c) {
+    for (int c = 1; c < cols_in; ++c) {
       const int cxp = c - 1 - a.dx_min;
-      const uint32_t pre_up = om[min(ms + lane, T - 1)];
+      const uint32_t pre_up = om[min(ms + lane, Tv - 1)];
       const uint32_t pre_dn = om[max(ms - 64 + lane, 0)];
       const int cnt_new = k + hstep_delta(cxp, cy, ms, a, I, hrow);
-      ms = scan_core<SHAPE>(ms, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), a, om,
-                            rsp, blocks, pre_up, pre_dn);
+      ms = scan_core<SHAPE>(ms, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
+                            om, rsp, blocks, pre_up, pre_dn);
+      if (BR && ms < mlo) {
+        failed = true;
+        break;
+      }
       m = set_lane(ms, s * tw + c, m);
     }
   }
   if (a.counters) seed_taps = seeds;  // taps per seed added on the host
   const long long clk2 = a.counters ? (long long)clock64() : 0;
-  {
+  if (!failed) {
     const int gx = tx0 + col, gy = ty0 + row0;
-    if (lane < segs * tw && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m);
+    if (lane < segs * tw && col < cols_in && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
   }
 
-  // 4b. vertical sweep down each band
-  const int lane_active = lane < segs * tw;
-  for (int r = 1; r < R; ++r) {
+  // 4b. vertical sweep down each band (lanes whose column or row is
+  // outside the image sit out)
+  const bool in_cols = lane < segs * tw && col < cols_in;
+  const int rows_in = a.h - (ty0 + row0);   // rows of this lane's band inside the image
+  const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, a.h - ty0 - wid * segs * R)));
+  for (int r = 1; r < r_end && !failed; ++r) {
+    const bool lane_active = in_cols && r < rows_in;
     const int cy_prev = row0 + r - 1 - a.dy_min;
     const int lbase = cy_prev * a.pitch + cxl;
     int delta = 0;
@@ -489,7 +612,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     int mnew = m;
     const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
     if (lane_active)
-      mnew = lane_select<SHAPE>(pl, cl, k, cxy, kLaneBudget, a, om, rsp, groups);
+      mnew = lane_select<SHAPE>(pl, cl, k, cxy, kLaneBudget, Tv, a, om, rsp, groups);
     uint64_t left = __ballot(lane_active && mnew < 0);
     while (left) {
       const int L = __ffsll((unsigned long long)left) - 1;
@@ -497,13 +620,18 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
       const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
       const int mL = scan_select<KT, SHAPE>(__builtin_amdgcn_readlane(pl, L),
                                             __builtin_amdgcn_readlane(cl, L), k, cxyL & 0xffff,
-                                            cxyL >> 16, a, om, rsp, blocks);
+                                            cxyL >> 16, Tv, a, om, rsp, blocks);
       mnew = set_lane(mL, L, mnew);
+    }
+    if (BR && __ballot(lane_active && mnew < mlo)) {
+      failed = true;
+      break;
     }
     m = mnew;
     const int gx = tx0 + col, gy = ty0 + row0 + r;
-    if (lane_active && gx < a.w && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m);
+    if (lane_active) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
   }
+  if (BR && failed && lane == 0) atomicOr(&a.tile_fail[tile], 1);
 
   if (a.counters && lane == 0) {
     const long long clk3 = (long long)clock64();

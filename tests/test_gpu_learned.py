@@ -1,0 +1,155 @@
+"""GPU tests of the learned-bracket path: exactness at any fallback rate,
+forced fallback with wrong brackets, the exact set of recomputed tiles for
+injected brackets, the network forward pass against the float64 oracle, and
+a short training run."""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cnn as OC
+from oracle import footprints as OF
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import paper_2505_22938_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def net(mf):
+    n = mf.LearnedNet(seed=1)
+    yield n
+    n.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def tile_info(mf, w, h, dtype_code, fp):
+    tx, ty = mf.LearnedNet.tile_grid(w, h, dtype_code, fp)
+    p = mf.query_plan(w, h, dtype_code, fp)
+    return tx, ty, p["tile_w"], p["tile_h"]
+
+
+def brackets_dev(br):
+    return torch.from_numpy(np.ascontiguousarray(br.astype(np.int64).astype(np.uint32)
+                                                 .view(np.int32))).cuda()
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16"])
+def test_forced_fallback_wrong_brackets(mf, net, oracle_mod, dtype):
+    img = workloads.natural_u16(300, 200, seed=2)
+    if dtype == "u8":
+        img = (img >> 8).astype(np.uint8)
+    code = mf.MF_U8 if dtype == "u8" else mf.MF_U16
+    fp = mf.Footprint.disc(8)
+    tx, ty, tw, th = tile_info(mf, 300, 200, code, fp)
+    br = np.zeros((ty * tx, 2))
+    br[:, 1] = 0          # bracket [0, 0]: wrong for every tile of this image
+    out, fb = net.filter_bracketed(dev(img), fp, brackets_dev(br))
+    torch.cuda.synchronize()
+    exp = oracle_mod.filter(img, OF.disc(8), "clamp")
+    assert np.array_equal(out.cpu().numpy(), exp)
+    assert fb == 300 * 200
+
+
+def test_full_bracket_no_fallback(mf, net, oracle_mod):
+    img = workloads.natural_u16(257, 131, seed=3)
+    fp = mf.Footprint.ellipse(9, 4, 20)
+    tx, ty, tw, th = tile_info(mf, 257, 131, mf.MF_U16, fp)
+    br = np.zeros((ty * tx, 2))
+    br[:, 1] = 65535
+    out, fb = net.filter_bracketed(dev(img), fp, brackets_dev(br), boundary="mirror")
+    torch.cuda.synchronize()
+    assert fb == 0
+    assert np.array_equal(out.cpu().numpy(), oracle_mod.filter(img, OF.ellipse(9, 4, 20), "mirror"))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_injected_brackets_fail_exactly_where_medians_escape(mf, net, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    W, H = 320, 260
+    img = workloads.natural_u16(W, H, seed=10 + seed)
+    r = [4, 12, 20][seed]
+    fp = mf.Footprint.disc(r)
+    exp = oracle_mod.filter(img, OF.disc(r), "clamp")
+    tx, ty, tw, th = tile_info(mf, W, H, mf.MF_U16, fp)
+    br = np.zeros((ty * tx, 2), dtype=np.int64)
+    expect_fail = 0
+    for t in range(tx * ty):
+        x0, y0 = (t % tx) * tw, (t // tx) * th
+        med = exp[y0:y0 + th, x0:x0 + tw]
+        lo, hi = int(med.min()), int(med.max())
+        mode = rng.integers(0, 4)
+        if mode == 0:          # exact range: no failure
+            br[t] = (lo, hi)
+        elif mode == 1:        # generous: no failure
+            br[t] = (max(0, lo - 500), min(65535, hi + 500))
+        elif mode == 2:        # too high at the bottom: some median escapes
+            br[t] = (min(lo + 1, hi), hi) if hi > lo else (lo + 1, hi + 1)
+        else:                  # too low at the top
+            br[t] = (lo, max(hi - 1, lo)) if hi > lo else (lo - 1, hi - 1)
+        if not (br[t, 0] <= lo and hi <= br[t, 1]):
+            expect_fail += med.size
+    br = np.clip(br, 0, 65535)
+    out, fb = net.filter_bracketed(dev(img), fp, brackets_dev(br))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), exp)
+    assert fb == expect_fail
+
+
+def test_network_forward_matches_oracle(mf, oracle_mod):
+    n = mf.LearnedNet(seed=7)
+    params = n.get_params().astype(np.float64)
+    W = 32 * 9 * 32
+    offW = [0, W + 32, 2 * (W + 32), 3 * (W + 32)]
+    offB = [W, 2 * W + 32, 3 * W + 64, 3 * (W + 32) + 16 * 9 * 32]
+    # perturb the output layer so lo/hi differ from their biases
+    rng = np.random.default_rng(0)
+    params[offW[3]:offW[3] + 2 * 9 * 32] = rng.normal(0, 0.05, 2 * 9 * 32)
+    n.set_params(params.astype(np.float32))
+    img = workloads.natural_u16(130, 70, seed=5)
+    out = n.forward(dev(img), 16)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)[..., :2]
+    p32 = params.astype(np.float32).astype(np.float64)
+    h = OC.bf16_round(OC.cell_features(img, 16, 65535.0))
+    h = np.concatenate([h, np.zeros(h.shape[:2] + (30,))], axis=2)
+    for l in range(4):
+        cout = 32 if l < 3 else 16
+        w = OC.bf16_round(p32[offW[l]:offW[l] + cout * 9 * 32].reshape(cout, 3, 3, 32))
+        b = p32[offB[l]:offB[l] + cout]
+        pre = OC.conv3x3(h, w, b)
+        h = OC.bf16_round(np.maximum(pre, 0)) if l < 3 else pre
+    exp = h[..., :2]
+    assert np.allclose(got, exp, rtol=2e-2, atol=2e-3), float(np.abs(got - exp).max())
+    n.close()
+
+
+def test_training_decreases_loss_and_filter_stays_exact(mf, oracle_mod):
+    n = mf.LearnedNet(seed=3)
+    fp = mf.Footprint.disc(8)
+    imgs = [dev(workloads.natural_u16(256, 256, seed=100 + i)) for i in range(4)]
+    meds = [mf.median_filter(im, fp, "clamp") for im in imgs]
+    torch.cuda.synchronize()
+    losses = []
+    for step in range(60):
+        i = step % 4
+        losses.append(n.train_step(imgs[i], meds[i], 8, 3e-3))
+    assert np.mean(losses[-8:]) < 0.7 * np.mean(losses[:8]), losses[:4] + losses[-4:]
+    test = workloads.natural_u16(256, 256, seed=999)
+    n.set_margin(0.02)
+    out, fb = n.filter(dev(test), fp)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle_mod.filter(test, OF.disc(8), "clamp"))
+    assert 0 <= fb <= 256 * 256
+    n.close()
