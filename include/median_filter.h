@@ -187,7 +187,9 @@ int mf_set_tile_override(int tile_w, int tile_h);
  * calls accumulate into: [0] wave-cooperative omnigram blocks scanned
  * (64 ordinals each), [1] seed windows solved, [2] [3] [4] shader clocks summed over waves spent in load+sort,
  * in seeds and first band rows, and in vertical sweeps, [5] number of
- * waves summed, [6] lane-parallel 8-ordinal groups tested, [7] reserved.  enable = 0: stop counting and free
+ * waves summed, [6] lane-parallel 8-ordinal groups tested, [7] box pixels
+ * ranked by the ordinal transforms (the learned and bracketed filters count
+ * into the same counters).  enable = 0: stop counting and free
  * them.  enable = -1: copy the eight counters to the host array `out8`
  * (synchronous).  Not thread-safe against concurrent filter calls.
  * Counting adds a few scalar instructions per block. */

@@ -241,7 +241,8 @@ def set_tile_override(tile_w: int = 0, tile_h: int = 0):
 
 def work_counters(enable: int):
     """enable=1: start (and zero) the device work counters; 0: stop; -1: read
-    them -> [blocks scanned, seeds, clk sort, clk rows, clk sweeps, waves, 0, 0]."""
+    them -> [blocks scanned, seeds, clk sort, clk rows, clk sweeps, waves, lane groups,
+    pixels ranked]."""
     buf = (ctypes.c_ulonglong * 8)()
     _check("mf_work_counters", lib().mf_work_counters(int(enable),
                                                       ctypes.cast(buf, ctypes.c_void_p)))
@@ -409,6 +410,19 @@ class LearnedNet:
         h = ctypes.c_void_p()
         _check("mf_learned_create", lib().mf_learned_create(int(seed), ctypes.byref(h)))
         self._h = h
+
+    @classmethod
+    def load(cls, path: str):
+        """A network from an .npz written by train_bracket (params, margin)."""
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            params = z["params"]
+            margin = float(z["margin"])
+        net = cls(seed=0)
+        net.set_params(params)
+        net.set_margin(margin)
+        net.margin = margin
+        return net
 
     @staticmethod
     def param_count():

@@ -221,6 +221,7 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
   a.out = out;
   a.brackets = br;
   a.tile_fail = n->tile_fail;
+  a.counters = mf::work_counters_ptr();
   const long long ntiles = (long long)a.tiles_x * a.tiles_y;
   if (hipMemsetAsync(n->tile_fail, 0, ntiles * sizeof(int), s) != hipSuccess ||
       hipMemsetAsync(n->fail_px, 0, sizeof(unsigned long long), s) != hipSuccess)

@@ -73,6 +73,8 @@ unsigned long long* g_counters = nullptr;  // device work counters, enabled on r
 
 }  // namespace
 
+unsigned long long* work_counters_ptr() { return g_counters; }
+
 // Launch one plain filter with a complete plan `a` (geometry + image bound).
 int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream) {
   a.counters = g_counters;

@@ -100,6 +100,9 @@ void record_tuned_shape(int dtype, const mf_footprint* fp, int tw, int th, doubl
 int tune_cache_load(const char* path);
 int tune_cache_save(const char* path);
 
+// Device work counters of the plain engine (null when counting is off).
+unsigned long long* work_counters_ptr();
+
 // Tile-shape override (measurement): 0 = off.
 void get_override(int* tw, int* th);
 

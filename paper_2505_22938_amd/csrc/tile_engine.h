@@ -46,6 +46,7 @@ enum {
   CNT_CYC_SWEEP = 4,   // shader clocks per wave: vertical sweeps
   CNT_WAVES = 5,       // waves that reported clocks
   CNT_GROUPS = 6,      // lane-parallel 8-ordinal groups tested (summed over lanes)
+  CNT_SORTED = 7,      // box pixels ranked by the ordinal transform (summed over tiles)
   CNT_SLOTS = 8
 };
 
@@ -519,6 +520,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
                       om, KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
                       wsum);
   }
+  if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)
   if (t < 16) om[Tv + t] = 0xffff;
   if (BR && t == 16) om[0] = 0xffff;
