@@ -1,7 +1,8 @@
 """Benchmark: exact median filter, 4096x4096 uint16 natural-like image, disc r=32, clamp.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--radius R] [--size S]
-                    [--no-cpu] [--cpu-seconds T]
+                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned]
+                    [--weights PATH] [--copy-check]
 
 One step = one call of the plain filter over the whole image (every step of
 the hot path: tile load, ordinal transform, sliding and omnigram scans,
@@ -9,6 +10,18 @@ reverse map), with the input already resident in device memory.  Prints one
 JSON line.  The CPU-baseline leg times the brute-force oracle on a bounded
 sample of output pixels on the host cores and counts mismatches of the GPU
 output on that sample.
+
+Two comparison legs go into the same line:
+  batched  - 64 mixed images (w, h uniform in 128..2048, u8/u16/f32, disc
+             r uniform in 1..64, clamp): one replay of the captured persistent
+             launch against 64 sequential plain launches on one stream;
+  learned  - 2048x2048 uint16 (i.i.d. uniform, and the natural-like
+             generator), disc r = 16, 32, 64: CNN bracket proposal + bracketed
+             tiles + exact fallback against the plain filter, with the
+             fallback rate.
+Both compare every output pixel with the plain filter's and a random sample
+with the oracle.  --copy-check adds a 256 MiB device copy (three launches),
+whose hardware byte counters calibrate the filter's in a counter run.
 """
 
 from __future__ import annotations
@@ -27,6 +40,34 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T int32 VALU lane-ops/s
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+# Sources the plain kernel and its launch plan are built from.
+PLAIN_SOURCES = ("tile_engine.h", "tile_common.h", "mf_internal.h", "median_plain.hip",
+                 "plan.cpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "mf_plain_kernel_u16_4096x4096_disc_r32_hbm_bytes.md")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in PLAIN_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_22938_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l)
+        if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
@@ -51,6 +92,134 @@ def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
                 computed_px=npx)
 
 
+def _time_events(torch, fn, stream, reps):
+    """Per-call device time (ms) of fn() bracketed by events on `stream`."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def _oracle_sample(img_np, ofp, got, n, seed):
+    """Mismatches of `got` against the oracle at n random pixels."""
+    import oracle
+    h, w = img_np.shape
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, w, n)
+    ys = rng.integers(0, h, n)
+    exp = oracle.filter_points(img_np, ofp, xs, ys, "clamp", nthreads=oracle.default_threads())
+    a = got[ys, xs]
+    if a.dtype == np.float32:
+        return int((a.view(np.uint32) != exp.view(np.uint32)).sum())
+    return int((a != exp).sum())
+
+
+def leg_batched(torch, mf, reps, check_oracle, log):
+    """Mixed batch of 64 images: captured persistent launch vs sequential plain launches."""
+    import workloads
+    from oracle import footprints as OF
+    batch = workloads.mixed_batch(64, 3)
+    fps, items, plain_out = {}, [], []
+    for img_np, sp in batch:
+        r = sp["radius"]
+        if r not in fps:
+            fps[r] = mf.Footprint.disc(r)
+        img = torch.from_numpy(img_np).cuda()
+        items.append((img, torch.empty_like(img), fps[r], "clamp"))
+        plain_out.append(torch.empty_like(img))
+    px = sum(int(i[0].numel()) for i in items)
+    stream = torch.cuda.current_stream()
+
+    def plain_all():
+        for (img, _, fp, b), o in zip(items, plain_out):
+            mf.median_filter(img, fp, b, out=o)
+
+    plain_all()
+    torch.cuda.synchronize()
+    t_plain = _time_events(torch, plain_all, stream, reps)
+    plan = mf.BatchPlan(items)
+    side = torch.cuda.Stream()
+    plan.capture(side)
+    plan.replay(side)
+    side.synchronize()
+    t_batch = _time_events(torch, lambda: plan.replay(side), side, reps)
+    info = plan.info()
+    mism = sum(int((it[1] != o).sum()) for it, o in zip(items, plain_out))
+    omism, ochk = None, 0
+    if check_oracle:
+        omism = 0
+        for i, ((img_np, sp), it) in enumerate(zip(batch, items)):
+            omism += _oracle_sample(img_np, OF.disc(sp["radius"]), it[1].cpu().numpy(), 64, i)
+            ochk += 64
+    plan.close()
+    mp, mb = float(np.median(t_plain)), float(np.median(t_batch))
+    log(f"# batched: {px / 1e6:.1f} Mpx, plain {mp:.2f} ms, graph {mb:.2f} ms")
+    return {"images": 64, "megapixels": px / 1e6, "plain_sequential_ms": mp,
+            "graph_replay_ms": mb, "speedup_vs_plain": mp / mb,
+            "plain_mpx_s": px / 1e3 / mp, "batched_mpx_s": px / 1e3 / mb,
+            "mismatches_vs_plain": mism, "oracle_mismatches": omism, "oracle_checked_px": ochk,
+            "plan": info, "tiles": "same default plan choice for both forms (no tune cache)"}
+
+
+def leg_learned(torch, mf, weights, reps, check_oracle, log):
+    """2048x2048 uint16: learned bracket path vs the plain filter."""
+    import workloads
+    from oracle import footprints as OF
+    if not os.path.exists(weights):
+        return {"skipped": f"no trained weights at {os.path.relpath(weights, ROOT)}"}
+    net = mf.LearnedNet.load(weights)
+    stream = torch.cuda.current_stream()
+    S = 2048
+    rows = []
+    for kind in ("uniform", "natural"):
+        img_np = (workloads.uniform_u16(S, S, seed=4) if kind == "uniform"
+                  else workloads.natural_u16(S, S, seed=4))
+        img = torch.from_numpy(img_np).cuda()
+        ref = torch.empty_like(img)
+        out = torch.empty_like(img)
+        for r in (16, 32, 64):
+            fp = mf.Footprint.disc(r)
+            mf.median_filter(img, fp, "clamp", out=ref)
+            tp = _time_events(torch, lambda: mf.median_filter(img, fp, "clamp", out=ref), stream,
+                              reps)
+            mf.work_counters(1)
+            mf.median_filter(img, fp, "clamp", out=ref)
+            torch.cuda.synchronize()
+            cp = mf.work_counters(-1)
+            mf.work_counters(0)
+            row = {"image": kind, "radius": r, "plain_ms": float(np.median(tp))}
+            try:
+                _, fb = net.filter(img, fp, out=out)
+            except mf.MedianFilterError as e:
+                row["learned"] = f"unsupported: {e}"
+                rows.append(row)
+                continue
+            tl = _time_events(torch, lambda: net.filter(img, fp, out=out, count_fallback=False),
+                              stream, reps)
+            mf.work_counters(1)
+            net.filter(img, fp, out=out)
+            torch.cuda.synchronize()
+            cl = mf.work_counters(-1)
+            mf.work_counters(0)
+            row.update(learned_ms=float(np.median(tl)), fallback_rate=fb / (S * S),
+                       speedup_vs_plain=row["plain_ms"] / float(np.median(tl)),
+                       ranked_px_fraction=cl[7] / max(cp[7], 1),
+                       mismatches_vs_plain=int((out != ref).sum()))
+            if check_oracle:
+                row["oracle_mismatches"] = _oracle_sample(img_np, OF.disc(r), out.cpu().numpy(),
+                                                          2000, r)
+            log(f"# learned {kind} r={r}: plain {row['plain_ms']:.3f} ms, learned "
+                f"{row['learned_ms']:.3f} ms, fallback {row['fallback_rate']:.4f}")
+            rows.append(row)
+    net.close()
+    return {"weights": os.path.relpath(weights, ROOT), "margin": net.margin,
+            "size": [S, S], "dtype": "u16", "results": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,7 +229,12 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--legs", default="plain,batched,learned")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
+                                                      "bracket_net.npz"))
+    ap.add_argument("--copy-check", action="store_true")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -119,9 +293,24 @@ def main():
     achieved = wm["total"] / (kmean * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Top/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-                "traffic": None, "kernel_ms_mean": kmean, "kernel_ms_min": float(np.min(kern_ms)),
+                "traffic": measured_traffic() if (S, r) == (4096, 32) else None, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel_ms_mean": kmean, "kernel_ms_min": float(np.min(kern_ms)),
                 "work_lane_ops": wm, "clocks_per_wave": phase_clk}
     gpu_out = out.cpu().numpy()
+
+    if args.copy_check:
+        # a plain device copy of known size, for calibrating byte counters
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    batched = leg_batched(torch, mf, 5, not args.no_cpu, log) if "batched" in legs else None
+    learned = (leg_learned(torch, mf, args.weights, 5, not args.no_cpu, log)
+               if "learned" in legs else None)
 
     cpu = None
     mismatches = None
@@ -161,6 +350,8 @@ def main():
                    "lds_bytes": plan["lds_bytes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "learned": learned,
     }
     print(json.dumps(line))
 

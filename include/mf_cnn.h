@@ -92,6 +92,10 @@ int mf_learned_param_count(void);
  * Adam state. */
 int mf_learned_get_params(const mf_learned* net, float* host);
 int mf_learned_set_params(mf_learned* net, const float* host);
+/* Host float32 copy of the parameter gradient of the last train step
+ * (synchronous; same layout as the parameters; the loss is the pinball loss
+ * summed over cells).  Zero before the first step. */
+int mf_learned_get_grads(const mf_learned* net, float* host);
 /* Bracket margin added on both sides, in units of the dtype's full range
  * (calibrated on held-out images by the caller). */
 int mf_learned_set_margin(mf_learned* net, float margin);

@@ -82,6 +82,7 @@ def lib():
         "mf_learned_param_count": ([], I),
         "mf_learned_get_params": ([P, P], I),
         "mf_learned_set_params": ([P, P], I),
+        "mf_learned_get_grads": ([P, P], I),
         "mf_learned_set_margin": ([P, ctypes.c_float], I),
         "mf_learned_forward": ([P, P, I, I, SZ, I, I, P, P], I),
         "mf_learned_train_step": ([P, P, P, I, I, SZ, I, I, ctypes.c_float,
@@ -435,6 +436,13 @@ class LearnedNet:
                                                                     a.ctypes.data_as(ctypes.c_void_p)))
         return a
 
+    def get_grads(self):
+        import numpy as np
+        a = np.empty(self.param_count(), dtype=np.float32)
+        _check("mf_learned_get_grads", lib().mf_learned_get_grads(self._h,
+                                                                  a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
     def set_params(self, a):
         import numpy as np
         a = np.ascontiguousarray(a, dtype=np.float32)
@@ -463,8 +471,11 @@ class LearnedNet:
             ctypes.byref(loss), _stream_ptr(stream)))
         return loss.value
 
-    def filter(self, img, fp: Footprint, boundary: str = "clamp", out=None, stream=None):
-        """Exact median via learned brackets; returns (out, fallback_pixels)."""
+    def filter(self, img, fp: Footprint, boundary: str = "clamp", out=None, stream=None,
+               count_fallback: bool = True):
+        """Exact median via learned brackets; returns (out, fallback_pixels).
+        With count_fallback=False the call stays asynchronous and the count
+        is None."""
         import torch
         code, es, w, h, sb = _plane_args(img)
         if out is None:
@@ -472,8 +483,8 @@ class LearnedNet:
         fb = ctypes.c_ulonglong()
         _check("median_filter_learned", lib().median_filter_learned(
             _p(img), w, h, sb, code, fp.handle, BOUNDARY[boundary], self._h, _p(out),
-            ctypes.byref(fb), _stream_ptr(stream)))
-        return out, fb.value
+            ctypes.byref(fb) if count_fallback else None, _stream_ptr(stream)))
+        return out, (fb.value if count_fallback else None)
 
     def filter_bracketed(self, img, fp: Footprint, brackets, boundary: str = "clamp", out=None,
                          stream=None):

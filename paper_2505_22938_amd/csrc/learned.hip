@@ -297,7 +297,8 @@ int mf_learned_set_params(mf_learned* n, const float* host) {
   if (hipMemcpy(n->p, host, mf::kParams * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(n->wbf, bf.data(), mf::kParams * 2, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(n->m, 0, mf::kParams * 4) != hipSuccess ||
-      hipMemset(n->v, 0, mf::kParams * 4) != hipSuccess)
+      hipMemset(n->v, 0, mf::kParams * 4) != hipSuccess ||
+      hipMemset(n->g, 0, mf::kParams * 4) != hipSuccess)
     return MF_ERR_HIP;
   n->step = 0;
   return MF_OK;
@@ -306,6 +307,12 @@ int mf_learned_set_params(mf_learned* n, const float* host) {
 int mf_learned_get_params(const mf_learned* n, float* host) {
   if (!n || !host) return MF_ERR_INVALID_ARG;
   return hipMemcpy(host, n->p, mf::kParams * 4, hipMemcpyDeviceToHost) == hipSuccess ? MF_OK
+                                                                                      : MF_ERR_HIP;
+}
+
+int mf_learned_get_grads(const mf_learned* n, float* host) {
+  if (!n || !host) return MF_ERR_INVALID_ARG;
+  return hipMemcpy(host, n->g, mf::kParams * 4, hipMemcpyDeviceToHost) == hipSuccess ? MF_OK
                                                                                       : MF_ERR_HIP;
 }
 

@@ -153,3 +153,64 @@ def test_training_decreases_loss_and_filter_stays_exact(mf, oracle_mod):
     assert np.array_equal(out.cpu().numpy(), oracle_mod.filter(test, OF.disc(8), "clamp"))
     assert 0 <= fb <= 256 * 256
     n.close()
+
+
+def _layer_slices():
+    W = 32 * 9 * 32
+    offW = [0, W + 32, 2 * (W + 32), 3 * (W + 32)]
+    offB = [W, 2 * W + 32, 3 * W + 64, 3 * (W + 32) + 16 * 9 * 32]
+    return offW, offB
+
+
+def test_train_step_gradient_matches_oracle(mf):
+    """One training step's parameter gradient against the float64 oracle's
+    backward pass, with bf16 rounding applied where the kernels store bf16
+    (weights, features, hidden activations, output and hidden gradients)."""
+    offW, offB = _layer_slices()
+    n = mf.LearnedNet(seed=5)
+    params = n.get_params().astype(np.float64)
+    rng = np.random.default_rng(1)
+    params[offW[3]:offW[3] + 2 * 9 * 32] = rng.normal(0, 0.05, 2 * 9 * 32)
+    for l in range(3):
+        params[offB[l]:offB[l] + 32] = rng.normal(0, 0.05, 32)
+    params[offB[3]:offB[3] + 2] = (0.3, 0.7)
+    n.set_params(params.astype(np.float32))
+    img = workloads.natural_u16(96, 72, seed=8)
+    d_img = dev(img)
+    med = mf.median_filter(d_img, mf.Footprint.disc(8), "clamp")
+    loss = n.train_step(d_img, med, 8, 1e-7)
+    torch.cuda.synchronize()
+    g = n.get_grads().astype(np.float64)
+    med_np = med.cpu().numpy()
+
+    p32 = params.astype(np.float32).astype(np.float64)
+    Ws, bs = [], []
+    for l in range(4):
+        cout = 32 if l < 3 else 16
+        Ws.append(OC.bf16_round(p32[offW[l]:offW[l] + cout * 9 * 32].reshape(cout, 3, 3, 32)))
+        bs.append(p32[offB[l]:offB[l] + cout])
+    f = OC.bf16_round(OC.cell_features(img, 8, 65535.0))
+    h = np.concatenate([f, np.zeros(f.shape[:2] + (30,))], axis=2)
+    cache = []
+    for l in range(4):
+        pre = OC.conv3x3(h, Ws[l], bs[l])
+        cache.append((h, pre))
+        h = OC.bf16_round(np.maximum(pre, 0)) if l < 3 else pre
+    t_lo, t_hi = OC.cell_targets(med_np, 65535.0)
+    L, gout = OC.loss_and_grad(h[..., :2], t_lo, t_hi)
+    ncell = t_lo.size
+    assert loss == pytest.approx(L, rel=1e-3)
+    d = np.zeros(h.shape[:2] + (16,))
+    d[..., :2] = OC.bf16_round(gout * ncell)
+    for l in range(3, -1, -1):
+        cout = 32 if l < 3 else 16
+        h_in, _ = cache[l]
+        dx, dw, db = OC.conv3x3_backward(h_in, Ws[l], d)
+        gw = g[offW[l]:offW[l] + cout * 9 * 32].reshape(cout, 3, 3, 32)
+        gb = g[offB[l]:offB[l] + cout]
+        for name, got, exp in (("W", gw, dw), ("b", gb, db)):
+            err = np.linalg.norm(got - exp) / max(np.linalg.norm(exp), 1e-30)
+            assert err < 2e-2, (l, name, err, np.linalg.norm(exp))
+        if l > 0:
+            d = OC.bf16_round(dx * (cache[l - 1][1] > 0))
+    n.close()
