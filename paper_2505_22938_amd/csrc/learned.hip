@@ -35,14 +35,14 @@ constexpr int kParams = 3 * (kW + 32) + kW4 + 16;
 template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  tile_body<KT, SHAPE, IMAX, false, true>(a, blockIdx.x, smem, nullptr);
+  tile_body<KT, SHAPE, IMAX, false, true>(a, xcd_tile(blockIdx.x, gridDim.x), smem, nullptr);
 }
 
 template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc a,
                                                                unsigned long long* fail_px) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (a.tile_fail[tile] == 0) return;   // uniform per workgroup
   tile_body<KT, SHAPE, IMAX, false, false>(a, tile, smem, nullptr);
   if (threadIdx.x == 0) {

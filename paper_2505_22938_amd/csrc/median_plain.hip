@@ -24,7 +24,7 @@ namespace mf {
 template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_plain_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  tile_body<KT, SHAPE, IMAX, false>(a, blockIdx.x, smem, nullptr);
+  tile_body<KT, SHAPE, IMAX, false>(a, xcd_tile(blockIdx.x, gridDim.x), smem, nullptr);
 }
 
 // Large boxes: a persistent grid, one global scratch slot per workgroup.
@@ -33,8 +33,8 @@ __global__ __launch_bounds__(kThreads) void mf_plain_gs_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* slot = a.scratch + (long long)blockIdx.x * a.slot_bytes;
   const int ntiles = a.tiles_x * a.tiles_y;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    tile_body<KT, SHAPE, 1, true>(a, tile, smem, slot);
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    tile_body<KT, SHAPE, 1, true>(a, xcd_tile(v, ntiles), smem, slot);
     __syncthreads();
   }
 }

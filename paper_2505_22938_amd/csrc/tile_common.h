@@ -10,6 +10,15 @@
 
 namespace mf {
 
+// Workgroups are dealt to the 8 XCDs round-robin by id.  Give XCD x a
+// contiguous run of tiles instead, so neighbouring tiles, which read the same
+// halo rows and columns, are processed under one L2.  Bijective on [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, j = b / kXcd, q = n / kXcd, rem = n % kXcd;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
+}
+
 // Boundary rule: clamp repeats the edge pixel; mirror reflects about it
 // without repeating it and folds with period 2(n-1).
 __device__ __forceinline__ int remap(int x, int n, int boundary) {
