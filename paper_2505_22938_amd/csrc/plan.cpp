@@ -133,13 +133,15 @@ int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   const int ib = round_up(2 * d->pitch * d->bh, 16);
   const int hb = kWaves * 128 * 4;
   const int B = std::max(kCounterBytes, ib + hb);
-  // slot: x0 (8 TP bytes of 64-bit words; after the sort omega + C16, or
-  // C32 + omega), x1 (8 TP), per-element byte ranks (T)
+  // slot: x0 and x1, TP words each (32-bit words for 8/16-bit keys, 64-bit
+  // for float keys); after the sort x0 holds omega (u16) + C16, or C32 +
+  // omega
+  const int wb = dtype == MF_F32 ? 8 : 4;
   d->off_p = 4 * TP;
   d->off_C = dtype == MF_F32 ? 0 : 2 * TP;
-  d->off_x1 = 8 * TP;
-  d->off_lr = 16 * TP;
-  d->slot_bytes = round_up(16 * TP + T, 256);
+  d->off_x1 = wb * TP;
+  d->off_lr = 0;
+  d->slot_bytes = round_up(2 * wb * TP, 256);
   d->ipt = (T + kThreads - 1) / kThreads;
   d->off_B = 0;
   d->off_hist = ib;

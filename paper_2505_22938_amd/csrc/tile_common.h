@@ -182,44 +182,55 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
 
 // Radix sort of one tile through global memory, for boxes whose sort does
 // not fit in LDS.  Same LSD scheme and stability argument as
-// block_radix_sort, but elements are not held in registers: each pass reads
-// its input from one of two global buffers (ping-pong), recounts, and
-// scatters into the other; the per-element local rank is kept in a byte
-// array.  Elements are 64-bit words (key << 16 | location); the key occupies
-// bits [16 + shift0, 16 + shift0 + 4*passes).  `passes` is even, so the
-// final pass writes the x0 region: locations to omega[] and keys to
-// crev16[] (16-bit keys) or crev32[] (32-bit keys).  ipt = elements per
-// thread (ceil(T / kThreads)); elements are numbered blocked (thread t owns
-// [t*ipt, (t+1)*ipt)).
-__device__ __forceinline__ void global_radix_sort(uint64_t* x0, uint64_t* x1, uint8_t* lrank,
-                                                  int T, int ipt, int shift0, int passes,
+// Stable LSD radix sort of T elements in global memory, for boxes whose
+// sort exchange does not fit in LDS.  Elements are words (key << 16 |
+// location), 32-bit for 8/16-bit keys and 64-bit for 32-bit keys; the key
+// occupies bits [16, 16 + 4*passes).  Each pass ping-pongs between x0 and
+// x1; `passes` is even, so the final pass reads x1 and writes the x0 region:
+// locations to omega[] and keys to crev16[] (16-bit keys) or crev32[].
+//
+// Element e is visited by thread e % kThreads in chunk e / kThreads, so
+// every load is coalesced.  The stable rank of an element is the scanned
+// count of its digit over (chunk, wave) groups in element order plus its
+// rank among the lanes of its wave holding the same digit (four ballots).
+// Counters: cnt[(digit * nchunks + chunk) * kWaves + wave], u16; T <= 65535
+// and nchunks <= 64 keep them within 16 * 64 * kWaves entries.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  const uint64_t b0 = __ballot(d & 1u), b1 = __ballot(d & 2u), b2 = __ballot(d & 4u),
+                 b3 = __ballot(d & 8u), bv = __ballot(valid);
+  return bv & ((d & 1u) ? b0 : ~b0) & ((d & 2u) ? b1 : ~b1) & ((d & 4u) ? b2 : ~b2) &
+         ((d & 8u) ? b3 : ~b3);
+}
+
+template <typename W>
+__device__ __forceinline__ void global_radix_sort(W* x0, W* x1, int T, int passes,
                                                   uint16_t* omega, uint16_t* crev16,
                                                   uint32_t* crev32, uint16_t* cnt,
                                                   uint32_t* wsum) {
-  const int t = threadIdx.x;
-  const int e0 = t * ipt, e1 = min(T, e0 + ipt);
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int nchunks = (T + kThreads - 1) / kThreads;
+  const uint64_t lt = (1ull << lane) - 1ull;
   for (int pass = 0; pass < passes; ++pass) {
-    const uint64_t* src = (pass & 1) ? x1 : x0;
-    uint64_t* dst = (pass & 1) ? x0 : x1;
-    const int sh = 16 + shift0 + 4 * pass;
+    const W* src = (pass & 1) ? x1 : x0;
+    W* dst = (pass & 1) ? x0 : x1;
+    const int sh = 16 + 4 * pass;
     const bool last = pass + 1 == passes;
-    uint32_t c[16];
-#pragma unroll
-    for (int d = 0; d < 16; ++d) c[d] = 0;
-    for (int e = e0; e < e1; ++e) {
-      const uint32_t d = (uint32_t)(src[e] >> sh) & 15u;
-      uint32_t r = 0;
-#pragma unroll
-      for (int dd = 0; dd < 16; ++dd) {
-        if (dd == (int)d) {
-          r = c[dd];
-          c[dd] = r + 1;
-        }
-      }
-      lrank[e] = (uint8_t)r;
+    // zero the counters (16 entries per thread)
+    {
+      uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
+      row[0] = make_uint4(0, 0, 0, 0);
+      row[1] = make_uint4(0, 0, 0, 0);
     }
-#pragma unroll
-    for (int d = 0; d < 16; ++d) cnt[d * kThreads + t] = (uint16_t)c[d];
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const int e = c * kThreads + t;
+      const bool valid = e < T;
+      const W v = valid ? src[e] : (W)0;
+      const uint32_t d = (uint32_t)(v >> sh) & 15u;
+      const uint64_t peers = digit_peers(d, valid);
+      if (valid && (peers & ~lt) == (1ull << lane))   // highest lane of its digit group
+        cnt[(d * nchunks + c) * kWaves + wid] = (uint16_t)__popcll(peers);
+    }
     __syncthreads();
     {
       uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
@@ -242,16 +253,22 @@ __device__ __forceinline__ void global_radix_sort(uint64_t* x0, uint64_t* x1, ui
       row[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
     __syncthreads();
-    for (int e = e0; e < e1; ++e) {
-      const uint64_t v = src[e];
+    for (int c = 0; c < nchunks; ++c) {
+      const int e = c * kThreads + t;
+      const bool valid = e < T;
+      const W v = valid ? src[e] : (W)0;
       const uint32_t d = (uint32_t)(v >> sh) & 15u;
-      const uint32_t o = (uint32_t)cnt[d * kThreads + t] + lrank[e];
-      if (!last) {
-        dst[o] = v;
-      } else {
-        omega[o] = (uint16_t)v;
-        if (crev32) crev32[o] = (uint32_t)(v >> 16);
-        else crev16[o] = (uint16_t)(v >> 16);
+      const uint64_t peers = digit_peers(d, valid);
+      if (valid) {
+        const uint32_t o =
+            (uint32_t)cnt[(d * nchunks + c) * kWaves + wid] + (uint32_t)__popcll(peers & lt);
+        if (!last) {
+          dst[o] = v;
+        } else {
+          omega[o] = (uint16_t)v;
+          if (crev32) crev32[o] = (uint32_t)(v >> 16);
+          else crev16[o] = (uint16_t)(v >> 16);
+        }
       }
     }
     __syncthreads();

@@ -30,6 +30,8 @@
 //   out     C[m] for every output pixel inside the image.
 #pragma once
 
+#include <type_traits>
+
 #include "tile_common.h"
 
 namespace mf {
@@ -501,24 +503,26 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
       block_radix_sort<IMAX, false>(key, pos, Ts, sh, passes, kbuf, pbuf, om + mlo, crev + mlo,
                                     nullptr, cnt, wsum);
   } else {
-    // load the box straight into global scratch as 64-bit words
-    uint64_t* x0 = reinterpret_cast<uint64_t*>(gslot);
-    uint64_t* x1 = reinterpret_cast<uint64_t*>(gslot + a.off_x1);
+    // load the box straight into global scratch as (key << 16 | location)
+    // words: 32-bit for 8/16-bit keys, 64-bit for float keys
+    using W = typename std::conditional<KT == KEY_F32, uint64_t, uint32_t>::type;
+    W* x0 = reinterpret_cast<W*>(gslot);
+    W* x1 = reinterpret_cast<W*>(gslot + a.off_x1);
     for (int e = t; e < T; e += kThreads) {
       const int ly = e / a.bw, lx = e - ly * a.bw;
       const int gx = remap(gx0 + lx, a.w, a.boundary);
       const int gy = remap(gy0 + ly, a.h, a.boundary);
       const long long off = (long long)gy * a.stride + gx;
-      uint64_t kk;
+      W kk;
       if (KT == KEY_U8) kk = static_cast<const uint8_t*>(a.img)[off];
       else if (KT == KEY_U16) kk = static_cast<const uint16_t*>(a.img)[off];
-      else kk = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
-      x0[e] = (kk << 16) | (uint64_t)((ly << 8) | lx);
+      else kk = (W)f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+      x0[e] = (kk << 16) | (W)((ly << 8) | lx);
     }
     __syncthreads();
-    global_radix_sort(x0, x1, gslot + a.off_lr, T, a.ipt, 0, KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8,
-                      om, KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
-                      wsum);
+    global_radix_sort<W>(x0, x1, T, KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8, om,
+                         KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
+                         wsum);
   }
   if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)
