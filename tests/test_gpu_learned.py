@@ -214,3 +214,38 @@ def test_train_step_gradient_matches_oracle(mf):
         if l > 0:
             d = OC.bf16_round(dx * (cache[l - 1][1] > 0))
     n.close()
+
+
+def test_trained_network_gain_over_full_brackets(mf, oracle_mod):
+    """What the trained network buys: on i.i.d. uniform uint16 noise (the
+    learned-proposal workload) the committed network's brackets rank a small
+    fraction of the box pixels that the method without it (every tile
+    bracketed by the full range) must rank, with the output still exact."""
+    import os
+    path = os.path.join(os.path.dirname(mf.__file__), "weights", "bracket_net.npz")
+    net = mf.LearnedNet.load(path)
+    img_np = workloads.uniform(512, 384, "u16", 42)
+    img = dev(img_np)
+    ranked = {}
+    for r in (16, 32):
+        fp = mf.Footprint.disc(r)
+        exp = oracle_mod.filter(img_np, OF.disc(r), "clamp")
+        mf.work_counters(1)
+        out, fb = net.filter(img, fp)
+        torch.cuda.synchronize()
+        learned = mf.work_counters(-1)[7]
+        mf.work_counters(0)
+        assert np.array_equal(out.cpu().numpy(), exp)
+        tx, ty, _, _ = tile_info(mf, 512, 384, mf.MF_U16, fp)
+        full = np.zeros((tx * ty, 2))
+        full[:, 1] = 65535
+        mf.work_counters(1)
+        out2, fb2 = net.filter_bracketed(img, fp, brackets_dev(full))
+        torch.cuda.synchronize()
+        plain = mf.work_counters(-1)[7]
+        mf.work_counters(0)
+        assert fb2 == 0 and np.array_equal(out2.cpu().numpy(), exp)
+        ranked[r] = learned / plain
+        assert fb <= 0.1 * 512 * 384, (r, fb)
+    assert ranked[16] < 0.5 and ranked[32] < 0.5, ranked
+    net.close()
