@@ -113,24 +113,35 @@ int mf_learned_train_step(mf_learned* net, const void* img, const void* median, 
                           size_t stride_bytes, int dtype, int radius, float lr, float* loss,
                           hipStream_t stream);
 
-/* Tile grid the learned and bracketed filters use for this image. */
+/* Tile grid the learned and bracketed filters use for this image (tile
+ * size as mf_query_plan reports it), and the most in-bracket box pixels a
+ * tile can rank (a tile with more is recomputed whole by the plain engine).
+ * Any output pointer may be NULL. */
 int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
-                         int* tiles_y);
+                         int* tiles_y, int* bracket_capacity);
 
 /* Exact median filter of an 8/16-bit plane with caller-supplied per-tile
  * value brackets: tile_brackets (device) holds (lo, hi) pairs of unsigned
- * ints, tiles_x * tiles_y of them in row-major tile order.  Tiles whose
- * medians fall outside their bracket are recomputed by the plain engine,
- * so the output always equals median_filter's.  fallback_px (host, may be
- * NULL; if set the call synchronizes) receives the number of output pixels
- * in recomputed tiles.  `net` supplies workspace only. */
+ * ints, tiles_x * tiles_y of them in row-major tile order (lo > hi: no
+ * bracket, the tile is computed by the plain engine).  A tile ranks only
+ * its box pixels inside the bracket.  Output pixels whose median lies
+ * outside their tile's bracket are recomputed one by one (exact selection
+ * over the window), and tiles with more in-bracket pixels than the
+ * bracketed layout holds (mf_learned_tile_grid) are recomputed whole by the
+ * plain engine, so the output always equals median_filter's.  8/16-bit
+ * planes, any radius, w * h < 2^32.  fallback_px (host, may be NULL; if set
+ * the call synchronizes) receives the number of output pixels recomputed
+ * either way.  `net` supplies workspace only (grown on demand, which
+ * synchronizes the device). */
 int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, int dtype,
                             const mf_footprint* fp, int boundary, const unsigned int* tile_brackets,
                             mf_learned* net, void* out, unsigned long long* fallback_px,
                             hipStream_t stream);
 
 /* Learned filter: the network proposes the brackets (union of a tile's
- * cells, widened by the margin), then as median_filter_bracketed. */
+ * cells, widened by the margin; a bracket wider than half the value range
+ * is dropped and the tile computed by the plain engine), then as
+ * median_filter_bracketed. */
 int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, int dtype,
                           const mf_footprint* fp, int boundary, mf_learned* net, void* out,
                           unsigned long long* fallback_px, hipStream_t stream);

@@ -87,7 +87,7 @@ def lib():
         "mf_learned_forward": ([P, P, I, I, SZ, I, I, P, P], I),
         "mf_learned_train_step": ([P, P, P, I, I, SZ, I, I, ctypes.c_float,
                                    ctypes.POINTER(ctypes.c_float), P], I),
-        "mf_learned_tile_grid": ([I, I, I, P, IP, IP], I),
+        "mf_learned_tile_grid": ([I, I, I, P, IP, IP, IP], I),
         "median_filter_bracketed": ([P, I, I, SZ, I, P, I, P, P, P,
                                      ctypes.POINTER(ctypes.c_ulonglong), P], I),
         "median_filter_learned": ([P, I, I, SZ, I, P, I, P, P,
@@ -500,12 +500,15 @@ class LearnedNet:
         return out, fb.value
 
     @staticmethod
-    def tile_grid(w: int, h: int, dtype: int, fp: Footprint):
-        tx, ty = ctypes.c_int(), ctypes.c_int()
+    def tile_grid(w: int, h: int, dtype: int, fp: Footprint, with_capacity: bool = False):
+        """(tiles_x, tiles_y) of the bracketed filters; with_capacity also
+        returns the most in-bracket box pixels a tile can rank."""
+        tx, ty, cap = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check("mf_learned_tile_grid", lib().mf_learned_tile_grid(w, h, dtype, fp.handle,
                                                                   ctypes.byref(tx),
-                                                                  ctypes.byref(ty)))
-        return tx.value, ty.value
+                                                                  ctypes.byref(ty),
+                                                                  ctypes.byref(cap)))
+        return (tx.value, ty.value, cap.value) if with_capacity else (tx.value, ty.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

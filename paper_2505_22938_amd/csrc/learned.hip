@@ -32,51 +32,179 @@ constexpr int kOffW[4] = {0, kW + 32, 2 * (kW + 32), 3 * (kW + 32)};
 constexpr int kOffB[4] = {kW, 2 * kW + 32, 3 * kW + 64, 3 * (kW + 32) + kW4};
 constexpr int kParams = 3 * (kW + 32) + kW4 + 16;
 
-template <int KT, int SHAPE, int IMAX>
-__global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  tile_body<KT, SHAPE, IMAX, false, true>(a, xcd_tile(blockIdx.x, gridDim.x), smem, nullptr);
+__device__ __forceinline__ void count_fallback(const ImageDesc& a, int tile,
+                                               unsigned long long* fail_px) {
+  const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
+  const long long n = (long long)min(a.tw, a.w - tx0) * min(a.th, a.h - ty0);
+  atomicAdd(fail_px, (unsigned long long)n);
 }
 
-template <int KT, int SHAPE, int IMAX>
-__global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc a,
-                                                               unsigned long long* fail_px) {
+// Bracketed tiles: one workgroup per tile; writes the tile's fail flag
+// (median outside the bracket, or more in-bracket pixels than fit).
+template <int KT, int SHAPE>
+__global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a, int* tile_fail) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (a.tile_fail[tile] == 0) return;   // uniform per workgroup
-  tile_body<KT, SHAPE, IMAX, false, false>(a, tile, smem, nullptr);
-  if (threadIdx.x == 0) {
-    const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
-    const long long n = (long long)min(a.tw, a.w - tx0) * min(a.th, a.h - ty0);
-    atomicAdd(fail_px, (unsigned long long)n);
+  const bool bad = tile_body<KT, SHAPE, 1, false, true>(a, tile, smem, nullptr);
+  if (threadIdx.x == 0) tile_fail[tile] = bad ? 1 : 0;
+}
+
+// The plain pass recomputes flagged tiles in sub-tiles (the bracketed tile
+// split rx x ry ways), so a failed tile's work spreads over several
+// workgroups instead of one tile time at the end.  Sub-tile `sub` of the
+// plain plan lies in bracketed tile `parent`.
+__device__ __forceinline__ int parent_tile(const ImageDesc& f, int sub, int parent_tiles_x, int rx,
+                                           int ry) {
+  return ((sub / f.tiles_x) / ry) * parent_tiles_x + (sub % f.tiles_x) / rx;
+}
+
+// Plain pass over the flagged tiles, LDS variant: one workgroup per sub-tile.
+template <int KT, int SHAPE, int IMAX>
+__global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc f, const int* tile_fail,
+                                                               int parent_tiles_x, int rx, int ry,
+                                                               unsigned long long* fail_px) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int sub = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile_fail[parent_tile(f, sub, parent_tiles_x, rx, ry)] == 0) return;   // uniform
+  tile_body<KT, SHAPE, IMAX, false, false>(f, sub, smem, nullptr);
+  if (threadIdx.x == 0) count_fallback(f, sub, fail_px);
+}
+
+// Plain pass over the flagged tiles, global-scratch variant: a persistent
+// grid over the sub-tiles, one scratch slot per workgroup.
+template <int KT, int SHAPE>
+__global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
+                                                                  const int* tile_fail,
+                                                                  int parent_tiles_x, int rx,
+                                                                  int ry,
+                                                                  unsigned long long* fail_px) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* slot = f.scratch + (long long)blockIdx.x * f.slot_bytes;
+  const int nsub = f.tiles_x * f.tiles_y;
+  for (int v = blockIdx.x; v < nsub; v += gridDim.x) {
+    const int sub = xcd_tile(v, nsub);
+    if (tile_fail[parent_tile(f, sub, parent_tiles_x, rx, ry)] == 0) continue;   // uniform
+    tile_body<KT, SHAPE, 1, true>(f, sub, smem, slot);
+    if (threadIdx.x == 0) count_fallback(f, sub, fail_px);
+    __syncthreads();
   }
 }
 
-// Tile bracket = union of its cells' predicted brackets, widened by
-// `margin` (normalised units), in value keys clamped to [0, maxval].
-__global__ void bracket_kernel(const float* __restrict__ out, int hc, int wc, int tw, int th,
-                               int tiles_x, int ntiles, float maxval, float margin,
-                               uint2* __restrict__ br) {
-  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tile >= ntiles) return;
+// Per-pixel exact fallback: one wave per listed pixel (index y * w + x)
+// selects the rank-k value of its window straight from the image by radix
+// selection on the value bits: a 256-bin histogram of the top byte finds
+// the byte holding rank k, then (16-bit) a histogram of the low byte among
+// the values with that top byte.  Adds the list length to fail_px.
+template <int KT>
+__global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
+                                                              const unsigned int* miss,
+                                                              const unsigned int* miss_count,
+                                                              unsigned long long* fail_px) {
+  __shared__ uint32_t hist_s[4][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t* hist = hist_s[wid];
+  const int n = (int)*miss_count;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(fail_px, (unsigned long long)n);
+  const int nwaves = (int)gridDim.x * 4;
+  constexpr int kPasses = KT == KEY_U8 ? 1 : 2;
+  for (int i = (int)blockIdx.x * 4 + wid; i < n; i += nwaves) {
+    const uint32_t idx = miss[i];
+    const int y = (int)(idx / (uint32_t)f.w), x = (int)(idx - (uint32_t)y * (uint32_t)f.w);
+    int target = f.rank;
+    uint32_t prefix = 0;
+    for (int pass = 0; pass < kPasses; ++pass) {
+      const int sh = (kPasses - 1 - pass) * 8;
+      for (int b = lane; b < 256; b += 64) hist[b] = 0;
+      wave_lds_sync();
+      for (int r = 0; r < f.nrows; ++r) {
+        const short2 sp = f.spans[r];
+        const long long rowoff = (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
+        for (int dx = sp.x + lane; dx <= sp.y; dx += 64) {
+          const int gx = remap(x + dx, f.w, f.boundary);
+          const uint32_t v = KT == KEY_U8
+                                 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
+                                 : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
+          if (pass == 1 && (v >> 8) != prefix) continue;
+          atomicAdd(&hist[(v >> sh) & 255u], 1u);
+        }
+      }
+      wave_lds_sync();
+      uint32_t h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = hist[lane * 4 + j];
+      const uint32_t sum = h[0] + h[1] + h[2] + h[3];
+      uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
+      int bin = -1;
+      uint32_t base = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (bin < 0 && cum <= (uint32_t)target && (uint32_t)target < cum + h[j]) {
+          bin = lane * 4 + j;
+          base = cum;
+        }
+        cum += h[j];
+      }
+      const uint64_t who = __ballot(bin >= 0);
+      const int src = __ffsll((unsigned long long)who) - 1;   // rank k always exists
+      const int sbin = __builtin_amdgcn_readlane(bin, src);
+      target -= __builtin_amdgcn_readlane((int)base, src);
+      prefix = pass == 0 ? (uint32_t)sbin : ((prefix << 8) | (uint32_t)sbin);
+      wave_lds_sync();
+    }
+    if (lane == 0) {
+      const long long o = (long long)y * f.stride + x;
+      if (KT == KEY_U8) static_cast<uint8_t*>(f.out)[o] = (uint8_t)prefix;
+      else static_cast<uint16_t*>(f.out)[o] = (uint16_t)prefix;
+    }
+  }
+}
+
+// One wave per tile: tile bracket = union of the predicted brackets of the
+// cells the tile covers, widened by `margin` (normalised units), rounded
+// outward to keys and clamped to [0, maxval].  Block 0 also clears the
+// fallback pixel count and the miss list.
+__global__ __launch_bounds__(256) void bracket_kernel(const float* __restrict__ out, int hc,
+                                                      int wc, int tw, int th, int tiles_x,
+                                                      int ntiles, float maxval, float margin,
+                                                      uint2* __restrict__ br,
+                                                      unsigned long long* fail_px,
+                                                      unsigned int* miss_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *fail_px = 0;
+    *miss_count = 0;
+  }
+  const int tile = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+  if (tile >= ntiles) return;   // uniform per wave
   const int tx0 = (tile % tiles_x) * tw, ty0 = (tile / tiles_x) * th;
   const int c0 = tx0 / 8, c1 = min(wc, (tx0 + tw + 7) / 8);
   const int r0 = ty0 / 8, r1 = min(hc, (ty0 + th + 7) / 8);
+  const int ncx = c1 - c0, ncell = ncx * (r1 - r0);
   float lo = 3.4e38f, hi = -3.4e38f;
-  for (int r = r0; r < r1; ++r)
-    for (int c = c0; c < c1; ++c) {
-      const float* o = out + ((long long)r * wc + c) * 16;
-      lo = fminf(lo, fminf(o[0], o[1]));
-      hi = fmaxf(hi, fmaxf(o[0], o[1]));
-    }
-  float L = floorf((lo - margin) * maxval), H = ceilf((hi + margin) * maxval);
-  L = fminf(fmaxf(L, 0.f), maxval);
-  H = fminf(fmaxf(H, 0.f), maxval);
-  if (!(L <= H)) {   // empty or NaN: no bracket
-    L = 0.f;
-    H = maxval;
+  for (int i = lane; i < ncell; i += 64) {
+    const int r = r0 + i / ncx, c = c0 + i % ncx;
+    const float2 v = *reinterpret_cast<const float2*>(out + ((long long)r * wc + c) * 16);
+    lo = fminf(lo, fminf(v.x, v.y));
+    hi = fmaxf(hi, fmaxf(v.x, v.y));
   }
-  br[tile] = make_uint2((unsigned)L, (unsigned)H);
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, d, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, d, 64));
+  }
+  if (lane == 0) {
+    float L = floorf((lo - margin) * maxval), H = ceilf((hi + margin) * maxval);
+    L = fminf(fmaxf(L, 0.f), maxval);
+    H = fminf(fmaxf(H, 0.f), maxval);
+    // empty, NaN, or wider than half the value range: no bracket (lo > hi),
+    // the tile goes straight to the plain pass
+    if (!(L <= H) || H - L > 0.5f * maxval) br[tile] = make_uint2(1u, 0u);
+    else br[tile] = make_uint2((unsigned)L, (unsigned)H);
+  }
+}
+
+// Caller-supplied brackets: clear the fallback count and the miss list.
+__global__ void clear_count_kernel(unsigned long long* fail_px, unsigned int* miss_count) {
+  *fail_px = 0;
+  *miss_count = 0;
 }
 
 }  // namespace mf
@@ -106,6 +234,10 @@ struct mf_learned {
   long long tiles_cap = 0;
   uint2* brackets = nullptr;
   int* tile_fail = nullptr;
+  // per-pixel misses: list of y * w + x, capacity miss_cap, count on device
+  unsigned int* miss = nullptr;
+  unsigned int* miss_count = nullptr;
+  long long miss_cap = 0;
   unsigned long long* fail_px = nullptr;
 };
 
@@ -174,6 +306,17 @@ int ensure_tiles(mf_learned* n, long long tiles) {
   return MF_OK;
 }
 
+int ensure_miss(mf_learned* n, long long px) {
+  if (px <= n->miss_cap) return MF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return MF_ERR_HIP;
+  (void)hipFree(n->miss);
+  n->miss = nullptr;
+  n->miss_cap = 0;
+  if (hipMalloc(&n->miss, px * sizeof(unsigned int)) != hipSuccess) return MF_ERR_NOMEM;
+  n->miss_cap = px;
+  return MF_OK;
+}
+
 int footprint_radius(const mf_footprint* fp) {
   return std::max(std::max(-fp->dx_min, fp->dx_max), std::max(-fp->dy_min, fp->dy_max));
 }
@@ -193,55 +336,112 @@ int net_forward(mf_learned* n, const void* img, int w, int h, size_t stride, int
                              nullptr, n->out, s);
 }
 
-using BrKernel = void (*)(mf::ImageDesc);
-using FbKernel = void (*)(mf::ImageDesc, unsigned long long*);
+using BrKernel = void (*)(mf::ImageDesc, int*);
+using FbKernel = void (*)(mf::ImageDesc, const int*, int, int, int, unsigned long long*);
 
 template <int KT, int SHAPE>
-void pick(int imax, BrKernel* b, FbKernel* f) {
-  switch (imax) {
-    case 9: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 9>; *f = mf::mf_fallback_kernel<KT, SHAPE, 9>; break;
-    case 17: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 17>; *f = mf::mf_fallback_kernel<KT, SHAPE, 17>; break;
-    case 25: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 25>; *f = mf::mf_fallback_kernel<KT, SHAPE, 25>; break;
-    default: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 33>; *f = mf::mf_fallback_kernel<KT, SHAPE, 33>; break;
+void pick(const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
+  *b = mf::mf_bracket_tile_kernel<KT, SHAPE>;
+  if (fb.gs) {
+    *f = mf::mf_fallback_gs_kernel<KT, SHAPE>;
+    return;
+  }
+  switch (fb.imax) {
+    case 9: *f = mf::mf_fallback_kernel<KT, SHAPE, 9>; break;
+    case 17: *f = mf::mf_fallback_kernel<KT, SHAPE, 17>; break;
+    case 25: *f = mf::mf_fallback_kernel<KT, SHAPE, 25>; break;
+    default: *f = mf::mf_fallback_kernel<KT, SHAPE, 33>; break;
   }
 }
 
-// Bracketed filter with per-tile brackets already in n->brackets (or the
-// caller's device array `br`), then the plain pass over flagged tiles.
+// Tile plans of the learned path: the bracketed layout `br` on the tile
+// shape the plain filter would use, and the plain layout `fb` (LDS if it
+// fits, else global scratch) of the fallback pass, on the largest sub-tile
+// shape (halved width and/or height) that is valid, rx x ry sub-tiles per
+// bracketed tile.
+struct LearnedPlan {
+  mf::ImageDesc br, fb;
+  mf::DeviceInfo di;
+  int dev, rx, ry;
+};
+
+int learned_plan(int dtype, const mf_footprint* fp, LearnedPlan* lp) {
+  if (hipGetDevice(&lp->dev) != hipSuccess) return MF_ERR_HIP;
+  int rc = mf::device_info(lp->dev, &lp->di);
+  if (rc) return rc;
+  mf::ImageDesc base{};
+  if ((rc = mf::choose_plan(dtype, fp, lp->di.lds_max, 33, &base))) return rc;
+  if ((rc = mf::make_plan_br(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->br)))
+    return rc;
+  const int tw = base.tw, th = base.th;
+  const int shapes[4][2] = {{tw / 2, th / 2}, {tw, th / 2}, {tw / 2, th}, {tw, th}};
+  for (const auto& sh : shapes) {
+    const int sw = sh[0], shh = sh[1];
+    if (sw < 1 || shh < 1 || tw % sw || th % shh) continue;
+    mf::ImageDesc f{};
+    if (mf::make_plan(dtype, fp, lp->di.lds_max, sw, shh, &f) != MF_OK || f.imax > 33)
+      if (mf::make_plan_gs(dtype, fp, lp->di.lds_max, sw, shh, &f) != MF_OK) continue;
+    lp->fb = f;
+    lp->rx = tw / sw;
+    lp->ry = th / shh;
+    return MF_OK;
+  }
+  return MF_ERR_UNSUPPORTED;
+}
+
+// Bracketed filter with per-tile brackets in `br` (the fallback count
+// already cleared on `s`), then the plain pass over the flagged tiles.
 int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int h,
                      size_t stride, int dtype, const mf_footprint* fp, int boundary, void* out,
-                     unsigned long long* fallback_px, hipStream_t s, const mf::ImageDesc& plan) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MF_ERR_HIP;
+                     unsigned long long* fallback_px, hipStream_t s, const LearnedPlan& lp) {
   const void* table = nullptr;
-  int rc = mf::footprint_device_table(fp, dev, &table);
+  int rc = mf::footprint_device_table(fp, lp.dev, &table);
   if (rc) return rc;
-  mf::ImageDesc a = plan;
-  mf::bind_image(&a, img, w, h, stride, dtype, fp, boundary, (fp->taps - 1) / 2, table);
-  a.out = out;
+  mf::ImageDesc a = lp.br, f = lp.fb;
+  const int rank = (fp->taps - 1) / 2;
+  mf::bind_image(&a, img, w, h, stride, dtype, fp, boundary, rank, table);
+  mf::bind_image(&f, img, w, h, stride, dtype, fp, boundary, rank, table);
+  a.out = f.out = out;
   a.brackets = br;
-  a.tile_fail = n->tile_fail;
-  a.counters = mf::work_counters_ptr();
+  a.miss = n->miss;
+  a.miss_count = n->miss_count;
+  a.counters = f.counters = mf::work_counters_ptr();
   const long long ntiles = (long long)a.tiles_x * a.tiles_y;
-  if (hipMemsetAsync(n->tile_fail, 0, ntiles * sizeof(int), s) != hipSuccess ||
-      hipMemsetAsync(n->fail_px, 0, sizeof(unsigned long long), s) != hipSuccess)
-    return MF_ERR_HIP;
   BrKernel bk = nullptr;
   FbKernel fk = nullptr;
   if (dtype == MF_U8) {
-    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U8, mf::SHAPE_DISC>(a.imax, &bk, &fk);
-    else pick<mf::KEY_U8, mf::SHAPE_SPANS>(a.imax, &bk, &fk);
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U8, mf::SHAPE_DISC>(f, &bk, &fk);
+    else pick<mf::KEY_U8, mf::SHAPE_SPANS>(f, &bk, &fk);
   } else {
-    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(a.imax, &bk, &fk);
-    else pick<mf::KEY_U16, mf::SHAPE_SPANS>(a.imax, &bk, &fk);
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(f, &bk, &fk);
+    else pick<mf::KEY_U16, mf::SHAPE_SPANS>(f, &bk, &fk);
+  }
+  const long long nsub = (long long)f.tiles_x * f.tiles_y;
+  long long fgrid = nsub;
+  if (f.gs) {
+    const int occ = std::max(1, std::min(2, lp.di.lds_max / std::max(1, f.lds_bytes)));
+    fgrid = std::min<long long>(nsub, (long long)lp.di.cus * occ);
+    void* scr = nullptr;
+    if ((rc = mf::get_scratch(lp.dev, s, (size_t)fgrid * (size_t)f.slot_bytes, &scr))) return rc;
+    f.scratch = static_cast<unsigned char*>(scr);
   }
   (void)hipFuncSetAttribute((const void*)bk, hipFuncAttributeMaxDynamicSharedMemorySize,
                             a.lds_bytes);
   (void)hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            a.lds_bytes);
-  hipLaunchKernelGGL(bk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a);
-  hipLaunchKernelGGL(fk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a,
-                     n->fail_px);
+                            f.lds_bytes);
+  hipLaunchKernelGGL(bk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a,
+                     n->tile_fail);
+  hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
+                     (const int*)n->tile_fail, a.tiles_x, lp.rx, lp.ry, n->fail_px);
+  const long long pgrid = std::max(1, lp.di.cus) * 4LL;
+  if (dtype == MF_U8)
+    hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,
+                       s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,
+                       n->fail_px);
+  else
+    hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U16>, dim3((unsigned)pgrid), dim3(256),
+                       0, s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,
+                       n->fail_px);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   if (fallback_px) {
     if (hipMemcpyAsync(fallback_px, n->fail_px, sizeof(unsigned long long), hipMemcpyDeviceToHost,
@@ -249,17 +449,6 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
         hipStreamSynchronize(s) != hipSuccess)
       return MF_ERR_HIP;
   }
-  return MF_OK;
-}
-
-int learned_plan(int dtype, const mf_footprint* fp, mf::ImageDesc* plan) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MF_ERR_HIP;
-  mf::DeviceInfo di;
-  int rc = mf::device_info(dev, &di);
-  if (rc) return rc;
-  if ((rc = mf::choose_plan(dtype, fp, di.lds_max, 33, plan))) return rc;
-  if (plan->gs || plan->T > 65534) return MF_ERR_UNSUPPORTED;
   return MF_OK;
 }
 
@@ -282,6 +471,8 @@ void mf_learned_destroy(mf_learned* n) {
   (void)hipFree(n->brackets);
   (void)hipFree(n->tile_fail);
   (void)hipFree(n->fail_px);
+  (void)hipFree(n->miss_count);
+  (void)hipFree(n->miss);
   delete n;
 }
 
@@ -331,7 +522,8 @@ int mf_learned_create(unsigned long long seed, mf_learned** out) {
       hipMalloc(&n->g, mf::kParams * 4) != hipSuccess ||
       hipMalloc(&n->wbf, mf::kParams * 2) != hipSuccess ||
       hipMalloc(&n->wflip, 32 * 9 * 32 * 2) != hipSuccess ||
-      hipMalloc(&n->fail_px, sizeof(unsigned long long)) != hipSuccess) {
+      hipMalloc(&n->fail_px, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&n->miss_count, sizeof(unsigned int)) != hipSuccess) {
     mf_learned_destroy(n);
     return MF_ERR_NOMEM;
   }
@@ -436,12 +628,18 @@ int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, 
     if (fallback_px) *fallback_px = 0;
     return MF_OK;
   }
-  mf::ImageDesc plan{};
-  if ((rc = learned_plan(dtype, fp, &plan))) return rc;
-  const long long ntiles = (long long)((w + plan.tw - 1) / plan.tw) * ((h + plan.th - 1) / plan.th);
-  if ((rc = ensure_tiles(net, ntiles))) return rc;
+  LearnedPlan lp;
+  if ((rc = learned_plan(dtype, fp, &lp))) return rc;
+  const long long ntiles =
+      (long long)((w + lp.br.tw - 1) / lp.br.tw) * ((h + lp.br.th - 1) / lp.br.th);
+  if (ntiles > 0x7fffffffLL) return MF_ERR_UNSUPPORTED;
+  if ((long long)w * h > 0xffffffffLL) return MF_ERR_UNSUPPORTED;
+  if ((rc = ensure_tiles(net, ntiles)) || (rc = ensure_miss(net, (long long)w * h))) return rc;
+  hipLaunchKernelGGL(mf::clear_count_kernel, dim3(1), dim3(1), 0, stream, net->fail_px,
+                     net->miss_count);
+  if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   return bracketed_filter(net, reinterpret_cast<const uint2*>(tile_brackets), img, w, h,
-                          stride_bytes, dtype, fp, boundary, out, fallback_px, stream, plan);
+                          stride_bytes, dtype, fp, boundary, out, fallback_px, stream, lp);
 }
 
 int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, int dtype,
@@ -454,30 +652,32 @@ int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, in
     if (fallback_px) *fallback_px = 0;
     return MF_OK;
   }
-  mf::ImageDesc plan{};
-  if ((rc = learned_plan(dtype, fp, &plan))) return rc;
-  const int tiles_x = (w + plan.tw - 1) / plan.tw, tiles_y = (h + plan.th - 1) / plan.th;
+  LearnedPlan lp;
+  if ((rc = learned_plan(dtype, fp, &lp))) return rc;
+  const int tiles_x = (w + lp.br.tw - 1) / lp.br.tw, tiles_y = (h + lp.br.th - 1) / lp.br.th;
   const long long ntiles = (long long)tiles_x * tiles_y;
-  if ((rc = ensure_tiles(net, ntiles))) return rc;
+  if (ntiles > 0x7fffffffLL / 64 || (long long)w * h > 0xffffffffLL) return MF_ERR_UNSUPPORTED;
+  if ((rc = ensure_tiles(net, ntiles)) || (rc = ensure_miss(net, (long long)w * h))) return rc;
   if ((rc = net_forward(net, img, w, h, stride_bytes, dtype, footprint_radius(fp), stream)))
     return rc;
   const float maxval = dtype == MF_U8 ? 255.0f : 65535.0f;
-  hipLaunchKernelGGL(mf::bracket_kernel, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0,
-                     stream, net->out, net->grid_h, net->grid_w, plan.tw, plan.th, tiles_x,
-                     (int)ntiles, maxval, net->margin, net->brackets);
+  hipLaunchKernelGGL(mf::bracket_kernel, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, stream,
+                     net->out, net->grid_h, net->grid_w, lp.br.tw, lp.br.th, tiles_x, (int)ntiles,
+                     maxval, net->margin, net->brackets, net->fail_px, net->miss_count);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   return bracketed_filter(net, net->brackets, img, w, h, stride_bytes, dtype, fp, boundary, out,
-                          fallback_px, stream, plan);
+                          fallback_px, stream, lp);
 }
 
 int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
-                         int* tiles_y) {
+                         int* tiles_y, int* bracket_capacity) {
   if (!fp || w <= 0 || h <= 0 || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
-  mf::ImageDesc plan{};
-  const int rc = learned_plan(dtype, fp, &plan);
+  LearnedPlan lp;
+  const int rc = learned_plan(dtype, fp, &lp);
   if (rc) return rc;
-  if (tiles_x) *tiles_x = (w + plan.tw - 1) / plan.tw;
-  if (tiles_y) *tiles_y = (h + plan.th - 1) / plan.th;
+  if (tiles_x) *tiles_x = (w + lp.br.tw - 1) / lp.br.tw;
+  if (tiles_y) *tiles_y = (h + lp.br.th - 1) / lp.br.th;
+  if (bracket_capacity) *bracket_capacity = lp.br.br_cap;
   return MF_OK;
 }
 

@@ -62,9 +62,13 @@ struct ImageDesc {
   // kernel selection: key type, shape, 1 = global-scratch variant, and the
   // register capacity (elements per thread) of the LDS variant
   int kt, shape, gs, imax;
-  // bracketed tiles (learned path): per-tile [lo, hi] keys and fail flags
+  // bracketed tiles (learned path): per-tile [lo, hi] keys, the number of
+  // in-bracket pixels region A can hold, and the list (y * w + x) and count
+  // of output pixels whose median fell outside their tile's bracket
   const uint2* brackets;
-  int* tile_fail;
+  int br_cap;
+  unsigned int* miss;
+  unsigned int* miss_count;
 };
 
 struct DeviceInfo {
@@ -80,6 +84,10 @@ int device_info(int dev, DeviceInfo* out);
 int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
 int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
 int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d);
+// Bracketed-tile plan (8/16-bit keys) for a given shape: region A holds only
+// the in-bracket pixels (up to br_cap of them), region B the ordinal image
+// of the whole box.  MF_ERR_UNSUPPORTED if fewer than 1024 fit.
+int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
 // Enumerate every valid plan (for the autotuner).
 std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int lds_max,
                                        int imax_cap);

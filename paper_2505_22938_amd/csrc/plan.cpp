@@ -125,6 +125,39 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   return MF_OK;
 }
 
+int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d) {
+  if (dtype != MF_U8 && dtype != MF_U16) return MF_ERR_UNSUPPORTED;
+  int rc = band_geometry(fp, tw, th, d);
+  if (rc) return rc;
+  const int T = d->T;
+  const int ib = round_up(2 * d->pitch * d->bh, 16);
+  const int hb = kWaves * 128 * 4;
+  const int B = std::max(kCounterBytes, ib + hb);
+  const int tb = table_bytes(d);
+  // region A: TPc 32-bit words (candidate exchange), afterwards omega and C
+  // (16-bit, ordinals 0..Tc plus 16 padding entries each)
+  const int avail = lds_max - B - tb;
+  if (avail <= 0) return MF_ERR_UNSUPPORTED;
+  int cap = (avail / 4) - 32;
+  cap = std::min(cap, std::min(T, 17 * kThreads));
+  if (cap < kThreads) return MF_ERR_UNSUPPORTED;
+  const int TPc = round_up(cap + 1, 8) + 16;
+  d->off_p = 0;
+  d->off_C = 2 * TPc;
+  d->off_B = 4 * TPc;
+  d->off_hist = d->off_B + ib;
+  d->off_tab = d->off_B + B;
+  d->lds_bytes = d->off_tab + tb;
+  d->kt = dtype;
+  d->gs = 0;
+  d->imax = 0;
+  d->slot_bytes = 0;
+  d->off_x1 = d->off_lr = d->ipt = 0;
+  d->br_cap = cap;
+  if (d->lds_bytes > lds_max) return MF_ERR_UNSUPPORTED;
+  return MF_OK;
+}
+
 int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d) {
   int rc = band_geometry(fp, tw, th, d);
   if (rc) return rc;
@@ -220,7 +253,8 @@ void bind_image(ImageDesc* d, const void* img, int w, int h, size_t stride_bytes
   d->counters = nullptr;
   d->scratch = nullptr;
   d->brackets = nullptr;
-  d->tile_fail = nullptr;
+  d->miss = nullptr;
+  d->miss_count = nullptr;
 }
 
 int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype,

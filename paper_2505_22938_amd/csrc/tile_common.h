@@ -180,8 +180,6 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
   }
 }
 
-// Radix sort of one tile through global memory, for boxes whose sort does
-// not fit in LDS.  Same LSD scheme and stability argument as
 // Stable LSD radix sort of T elements in global memory, for boxes whose
 // sort exchange does not fit in LDS.  Elements are words (key << 16 |
 // location), 32-bit for 8/16-bit keys and 64-bit for 32-bit keys; the key

@@ -95,19 +95,21 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
 // is used).
 // T bounds the valid ordinals ([0, T) here; entries beyond are padding).
 // Returns -1 if no member of rank k exists among the valid ordinals (only
-// possible when some pixels are outside the omnigram, see BR below).
+// possible when some pixels are outside the omnigram, see BR below); c_end
+// then receives the number of members below the end reached (below T going
+// up, below ordinal 0 going down).
 template <int SHAPE>
 __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int T,
                                          const ImageDesc& a, const uint16_t* om,
                                          const short2* rsp, int& blocks, uint32_t pre_up,
-                                         uint32_t pre_dn) {
+                                         uint32_t pre_dn, int& c_end) {
   const int lane = threadIdx.x & 63;
   const int cap = (T >> 6) + 2;
   if (c <= k) {
     int need = k - c;
     int b = p;
     uint32_t cur = pre_up;
-    for (int it = 0; it < cap; ++it, b += 64) {
+    for (int it = 0; it < cap && b < T; ++it, b += 64) {
       const uint32_t nxt = om[min(max(b + 64 + lane, 0), T - 1)];
       const bool in = b + lane < T &&
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
@@ -123,11 +125,12 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       need -= pc;
       cur = nxt;
     }
+    c_end = k - need;   // members below T
   } else {
     int need = c - k;
     int b = p;
     uint32_t cur = pre_dn;
-    for (int it = 0; it < cap; ++it, b -= 64) {
+    for (int it = 0; it < cap && b > 0; ++it, b -= 64) {
       const uint32_t nxt = om[max(b - 128 + lane, 0)];
       const int v = b - 64 + lane;
       const bool in = v >= 0 && v < T &&
@@ -145,6 +148,7 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       need -= pc;
       cur = nxt;
     }
+    c_end = k + need;   // members below ordinal 0
   }
   return -1;
 }
@@ -152,12 +156,12 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
 template <int KT, int SHAPE>
 __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, int T,
                                            const ImageDesc& a, const uint16_t* om,
-                                           const short2* rsp, int& blocks) {
+                                           const short2* rsp, int& blocks, int& c_end) {
   const int lane = threadIdx.x & 63;
   const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
   const bool up = c <= k;
   const uint32_t pre = up ? om[min(max(p + lane, 0), T - 1)] : om[max(p - 64 + lane, 0)];
-  return scan_core<SHAPE>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre);
+  return scan_core<SHAPE>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre, c_end);
 }
 
 // Lane-parallel rank selection: every lane refines its own window.  Same
@@ -250,19 +254,23 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 }
 
 // Seed solve for the window centred at box (cx, cy): histogram of its
-// ordinals >> hist_shift, pick the bin holding rank k, refine by scanning.
+// ordinals >> hshift, pick the bin holding rank k, refine by scanning.
 // BR (bracketed tiles): ordinal 0 stands for every pixel below the bracket
-// and 0xffff for every pixel above it; the top histogram bin absorbs the
-// latter, and a pivot in bin 0 starts at ordinal 1 with the exact count of
-// below-bracket pixels in the window.
+// and 0xffff for every pixel above it.  If the median is below (above) the
+// bracket, returns -1 with esc_p = 1 (T) and esc_c = the exact number of
+// window members below that ordinal, so sliding can go on from there.
 template <int KT, int SHAPE, bool BR>
-__device__ __forceinline__ int seed_solve(int cx, int cy, int T, const ImageDesc& a,
+__device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, const ImageDesc& a,
                                           const uint16_t* om, const uint16_t* I, uint32_t* hist,
-                                          const short2* rsp, int& blocks) {
+                                          const short2* rsp, int& blocks, int& esc_p,
+                                          int& esc_c) {
   const int lane = threadIdx.x & 63;
   const int k = a.rank;
   int zeros = 0;
-  // 256 bins of 16-bit counts, two per word (a window has < 65536 taps)
+  // 256 bins of 16-bit counts, two per word (a window has < 65536 taps).
+  // Bracketed tiles: pixels below the bracket (ordinal 0) are counted in a
+  // register and pixels above it (0xffff) skipped, so the histogram holds
+  // only in-bracket ordinals and no bin is hammered by atomics.
   hist[lane * 2] = 0;
   hist[lane * 2 + 1] = 0;
   wave_lds_sync();
@@ -271,15 +279,23 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, const ImageDesc
     const int row = (cy + a.dy_min + i) * a.pitch + cx;
     for (int x = s.x; x <= s.y; ++x) {
       const uint32_t iv = I[row + x];
-      uint32_t b = iv >> a.hist_shift;
       if (BR) {
-        b = min(b, 255u);
         zeros += iv == 0;
+        if (iv == 0 || iv == 0xffffu) continue;
       }
+      const uint32_t b = iv >> hshift;
       atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
     }
   }
+  if (BR)
+    for (int d = 32; d >= 1; d >>= 1) zeros += __shfl_xor(zeros, d, 64);
   wave_lds_sync();
+  const int target = k - zeros;   // rank among the histogram's entries
+  if (BR && target < 0) {          // median below the bracket
+    esc_p = 1;
+    esc_c = zeros;
+    return -1;
+  }
   const uint32_t w0 = hist[lane * 2], w1 = hist[lane * 2 + 1];
   uint32_t h[4] = {w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16};
   const uint32_t sum = h[0] + h[1] + h[2] + h[3];
@@ -288,24 +304,25 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, const ImageDesc
   uint32_t base = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (bin < 0 && cum <= (uint32_t)k && (uint32_t)k < cum + h[j]) {
+    if (bin < 0 && cum <= (uint32_t)target && (uint32_t)target < cum + h[j]) {
       bin = lane * 4 + j;
       base = cum;
     }
     cum += h[j];
   }
   const uint64_t who = __ballot(bin >= 0);
+  if (BR && who == 0) {             // median above the bracket
+    esc_p = T;
+    esc_c = zeros + __builtin_amdgcn_readlane((int)cum, 63);
+    return -1;
+  }
   const int src = __ffsll((unsigned long long)who) - 1;
   const int sbin = __builtin_amdgcn_readlane(bin, src);
-  int sbase = __builtin_amdgcn_readlane((int)base, src);
-  int p = sbin << a.hist_shift;
-  if (BR && p == 0) {
-    // ordinal 1 with the window's below-bracket count
-    for (int d = 32; d >= 1; d >>= 1) zeros += __shfl_xor(zeros, d, 64);
-    p = 1;
-    sbase = zeros;
-  }
-  return scan_select<KT, SHAPE>(p, sbase, k, cx, cy, T, a, om, rsp, blocks);
+  const int sbase = __builtin_amdgcn_readlane((int)base, src) + zeros;
+  int p = sbin << hshift;
+  if (BR && p == 0) p = 1;          // ordinal 1; entries below it are the zeros
+  int c_end = 0;
+  return scan_select<KT, SHAPE>(p, sbase, k, cx, cy, T, a, om, rsp, blocks, c_end);
 }
 
 // Count change when the window centred at box (cx, cy) moves right by one
@@ -347,6 +364,39 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
   if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m] + lo);
 }
 
+// Bracketed tiles: append the flagged output pixels of the wave (index
+// y * w + x) to the miss list.  Call with the whole wave.
+__device__ __forceinline__ void push_misses(const ImageDesc& a, bool missed, int gx, int gy) {
+  const uint64_t mb = __ballot(missed);
+  if (mb == 0) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(a.miss_count, (uint32_t)__popcll(mb));
+  base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+  if (missed)
+    a.miss[base + (uint32_t)__popcll(mb & ((1ull << lane) - 1ull))] = (uint32_t)gy * (uint32_t)a.w +
+                                                                       (uint32_t)gx;
+}
+
+// Bracketed tiles: sort the Ts candidate words held in kbuf (element e =
+// kbuf[e]) with ITEMS elements per thread; ordinals are written to
+// omega/crev from index 0 (callers pass the arrays shifted by one).
+template <int ITEMS>
+__device__ __forceinline__ void br_sort(uint32_t* kbuf, int Ts, int passes, uint16_t* omega,
+                                        uint16_t* crev, uint16_t* cnt, uint32_t* wsum) {
+  const int t = threadIdx.x;
+  uint32_t key[ITEMS];
+  uint16_t pos[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int e = i * kThreads + t;
+    key[i] = e < Ts ? kbuf[e] : 0u;
+    pos[i] = 0;
+  }
+  block_radix_sort<ITEMS, false>(key, pos, Ts, 16, passes, kbuf, nullptr, omega, crev, nullptr,
+                                 cnt, wsum);
+}
+
 // One output tile.  All threads of the workgroup must call it.
 // GS = false: the sort, the omnigram and the reverse map live in LDS.
 // GS = true: they live in the workgroup's global scratch slot `gslot`
@@ -355,11 +405,14 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 // BR = true (LDS variant only): the tile has a value bracket [lo, hi]
 // (a.brackets[tile], keys).  Only box pixels inside it are sorted; they take
 // ordinals 1..Tc, pixels below take ordinal 0 and pixels above 0xffff in the
-// ordinal image, so every count stays exact.  A window whose median is
-// outside the bracket cannot find a member of rank k among ordinals 1..Tc;
-// the tile is then flagged in a.tile_fail and left for the plain pass.
+// ordinal image, so every count stays exact.  A window whose median lies
+// outside the bracket has no member of rank k among ordinals 1..Tc: its
+// output pixel is appended to a.miss (to be recomputed by the per-pixel
+// pass) and the sweep goes on.  Returns true, with nothing written, if the
+// tile has more in-bracket pixels than region A holds (the caller then runs
+// the plain body on it); always false without BR.
 template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false>
-__device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned char* smem,
+__device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned char* smem,
                                           unsigned char* gslot) {
   static_assert(!(GS && BR), "bracketed tiles use the LDS variant");
   const int T = a.T;
@@ -406,8 +459,86 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
                         (s.x - 1) * a.pitch + dx, s.y * a.pitch + dx);
   }
 
-  uint64_t below_bits = 0, above_bits = 0;   // BR: classes of this thread's striped items
-  if constexpr (!GS) {
+  uint64_t below_bits = 0, above_bits = 0;   // BR: classes of this thread's chunks
+  if constexpr (BR) {
+    static_assert(KT != KEY_F32, "bracketed tiles take 8/16-bit keys");
+    if (blo > bhi) return true;   // no bracket: the plain pass takes the tile
+    // 1. stream the box in chunks of kThreads pixels (pixel e = chunk *
+    // kThreads + t).  Pixels inside the bracket are appended to the exchange
+    // buffer, keyed relative to the bracket's low end; the class of the
+    // others (below / above) is kept as bit `chunk` of two masks.
+    uint32_t* ncand = wsum + 24;
+    if (t == 0) *ncand = 0;
+    __syncthreads();
+    const int cap = a.br_cap;
+    const int nch = (T + kThreads - 1) / kThreads;   // <= 64
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // box coordinates of pixel c * kThreads + t, stepped per chunk
+    int lx = t % a.bw, ly = t / a.bw;
+    const int sx = kThreads % a.bw, sy = kThreads / a.bw;
+    constexpr int kBatch = 8;   // chunks whose loads are in flight together
+    for (int c0 = 0; c0 < nch; c0 += kBatch) {
+      uint32_t kv[kBatch], loc[kBatch];
+      bool valid[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const int e = (c0 + j) * kThreads + t;
+        valid[j] = c0 + j < nch && e < T;
+        loc[j] = (uint32_t)((ly << 8) | lx);
+        {
+          // unconditional: remap keeps every coordinate inside the image,
+          // so all kBatch loads are issued before the first use
+          const int gx = remap(gx0 + lx, a.w, a.boundary);
+          const int gy = remap(gy0 + ly, a.h, a.boundary);
+          const long long off = (long long)gy * a.stride + gx;
+          kv[j] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(a.img)[off]
+                               : (uint32_t)static_cast<const uint16_t*>(a.img)[off];
+        }
+        lx += sx;
+        ly += sy;
+        if (lx >= a.bw) {
+          lx -= a.bw;
+          ly += 1;
+        }
+      }
+      uint64_t bal[kBatch];
+      uint32_t total = 0;
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const bool below = valid[j] && kv[j] < blo, above = valid[j] && kv[j] > bhi;
+        if (c0 + j < 64) {
+          below_bits |= (uint64_t)below << (c0 + j);
+          above_bits |= (uint64_t)above << (c0 + j);
+        }
+        bal[j] = __ballot(valid[j] && !below && !above);
+        total += (uint32_t)__popcll(bal[j]);
+      }
+      uint32_t base = 0;
+      if (lane == 0 && total != 0) base = atomicAdd(ncand, total);
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const uint32_t o = base + (uint32_t)__popcll(bal[j] & lt);
+        if (((bal[j] >> lane) & 1ull) && o < (uint32_t)cap)
+          kbuf[o] = ((kv[j] - blo) << 16) | loc[j];
+        base += (uint32_t)__popcll(bal[j]);
+      }
+    }
+    __syncthreads();
+    const int Ts = (int)*ncand;
+    if (Ts > cap) return true;   // more in-bracket pixels than region A holds
+    // 2. ordinal transform of the candidates, ordinals 1..Ts; passes cover
+    // the bracket's span
+    const uint32_t span = bhi - blo;
+    int passes = 1;
+    while (passes < 4 && (span >> (4 * passes)) != 0) ++passes;
+    if (Ts <= 3 * kThreads) br_sort<3>(kbuf, Ts, passes, om + 1, crev + 1, cnt, wsum);
+    else if (Ts <= 9 * kThreads) br_sort<9>(kbuf, Ts, passes, om + 1, crev + 1, cnt, wsum);
+    else if (Ts <= 13 * kThreads) br_sort<13>(kbuf, Ts, passes, om + 1, crev + 1, cnt, wsum);
+    else br_sort<17>(kbuf, Ts, passes, om + 1, crev + 1, cnt, wsum);
+    Tv = Ts + 1;
+    mlo = 1;
+  } else if constexpr (!GS) {
     // 1. load the box (striped order)
     uint32_t key[IMAX];
     uint16_t pos[IMAX];
@@ -418,7 +549,9 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
       for (int i = 0; i < IMAX; ++i) {
         const int e = i * kThreads + t;
         uint32_t kk = 0, q = 0;
-        if (e < T) {
+        {
+          // unconditional load (remap keeps coordinates inside the image);
+          // elements numbered >= T are ignored by the sort
           const int gx = remap(gx0 + lx, a.w, a.boundary);
           const int gy = remap(gy0 + ly, a.h, a.boundary);
           const long long off = (long long)gy * a.stride + gx;
@@ -430,7 +563,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
             q = p;
           }
         }
-        key[i] = kk;
+        key[i] = e < T ? kk : 0u;
         pos[i] = (uint16_t)q;
         lx += sx;
         ly += sy;
@@ -440,68 +573,14 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
         }
       }
     }
-
-    int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
-    int Ts = T;   // elements sorted
-    if constexpr (BR) {
-      // keep the pixels inside the bracket, keyed relative to its low end
-      int ncand = 0;
-#pragma unroll
-      for (int i = 0; i < IMAX; ++i) {
-        const int e = i * kThreads + t;
-        const uint32_t kv = KT == KEY_F32 ? key[i] : key[i] >> 16;
-        const bool valid = e < T;
-        const bool below = valid && kv < blo, above = valid && kv > bhi;
-        below_bits |= (uint64_t)below << i;
-        above_bits |= (uint64_t)above << i;
-        ncand += valid && !below && !above;
-      }
-      const uint32_t base = block_exclusive_scan((uint32_t)ncand, wsum);
-      if (t == kThreads - 1) wsum[kWaves] = base + ncand;
-      int o = (int)base;
-#pragma unroll
-      for (int i = 0; i < IMAX; ++i) {
-        const int e = i * kThreads + t;
-        if (e < T && !((below_bits >> i) & 1) && !((above_bits >> i) & 1)) {
-          if (KT == KEY_F32) {
-            kbuf[o] = key[i] - blo;
-            pbuf[o] = pos[i];
-          } else {
-            kbuf[o] = key[i] - (blo << 16);
-          }
-          ++o;
-        }
-      }
-      __syncthreads();
-      Ts = (int)wsum[kWaves];
-#pragma unroll
-      for (int i = 0; i < IMAX; ++i) {
-        const int e = i * kThreads + t;
-        uint32_t kk = 0;
-        uint16_t q = 0;
-        if (e < Ts) {
-          kk = kbuf[e];
-          if (KT == KEY_F32) q = pbuf[e];
-        }
-        key[i] = kk;
-        pos[i] = q;
-      }
-      // passes: 4-bit digits covering hi - lo
-      const uint32_t span = bhi - blo;
-      passes = 1;
-      while (passes < (KT == KEY_F32 ? 8 : 4) && (span >> (4 * passes)) != 0) ++passes;
-      Tv = Ts + 1;
-      mlo = 1;
-    }
-
-    // 2. ordinal transform (BR: ordinals shifted by one)
-    const int sh = KT == KEY_F32 ? 0 : 16;
+    // 2. ordinal transform
+    const int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
     if (KT == KEY_F32)
-      block_radix_sort<IMAX, true>(key, pos, Ts, sh, passes, kbuf, pbuf, om + mlo, nullptr,
-                                   kbuf + mlo, cnt, wsum);
+      block_radix_sort<IMAX, true>(key, pos, T, 0, passes, kbuf, pbuf, om, nullptr, kbuf, cnt,
+                                   wsum);
     else
-      block_radix_sort<IMAX, false>(key, pos, Ts, sh, passes, kbuf, pbuf, om + mlo, crev + mlo,
-                                    nullptr, cnt, wsum);
+      block_radix_sort<IMAX, false>(key, pos, T, 16, passes, kbuf, pbuf, om, crev, nullptr, cnt,
+                                    wsum);
   } else {
     // load the box straight into global scratch as (key << 16 | location)
     // words: 32-bit for 8/16-bit keys, 64-bit for float keys
@@ -534,15 +613,20 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
   }
   if (BR) {
-    // pixels outside the bracket: striped item i of this thread is box
-    // element i * kThreads + t
-#pragma unroll
-    for (int i = 0; i < IMAX; ++i) {
-      const bool bl = (below_bits >> i) & 1, ab = (above_bits >> i) & 1;
-      if (bl || ab) {
-        const int e = i * kThreads + t;
-        const int ly = e / a.bw, lx = e - ly * a.bw;
-        I[ly * a.pitch + lx] = bl ? (uint16_t)0 : (uint16_t)0xffff;
+    // pixels outside the bracket: bit c of the masks is box pixel
+    // c * kThreads + t (coordinates stepped per chunk, as in the load)
+    const uint64_t rest = below_bits | above_bits;
+    const int nch = (T + kThreads - 1) / kThreads;
+    int lx = t % a.bw, ly = t / a.bw;
+    const int sx = kThreads % a.bw, sy = kThreads / a.bw;
+    for (int c = 0; c < nch; ++c) {
+      if ((rest >> c) & 1ull)
+        I[ly * a.pitch + lx] = ((below_bits >> c) & 1ull) ? (uint16_t)0 : (uint16_t)0xffff;
+      lx += sx;
+      ly += sy;
+      if (lx >= a.bw) {
+        lx -= a.bw;
+        ly += 1;
       }
     }
   }
@@ -551,6 +635,13 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
 
   // 4. bands
   const int k = a.rank;
+  // seed histogram bins: ordinals >> hshift (bracketed tiles: sized to the
+  // in-bracket ordinals)
+  int hshift = a.hist_shift;
+  if (BR) {
+    hshift = 0;
+    while (((Tv - 1) >> hshift) > 255) ++hshift;
+  }
   uint32_t* hist = hist_all + wid * 128;
   int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;
@@ -558,43 +649,63 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   const int band = wid * segs + seg;
   const int row0 = band * R;                 // first output row of this lane's band
   const int cxl = col - a.dx_min;            // lane's window centre, box coords
-  int m = 0;
-  bool failed = false;                       // BR: a median fell outside the bracket
+  // Lane state after each row: its window's median ordinal m, and a pivot
+  // vp with the exact number vc of window members below it (vp = m, vc = k
+  // normally).  BR: a window whose median is outside the bracket is a miss
+  // (recomputed per pixel afterwards); its pivot is then the bracket end it
+  // left by (ordinal 1 or Tv) with the exact count there, so sliding goes on
+  // and the median is picked up again once it re-enters the bracket.
+  int m = 0, vp = 0, vc = k, miss = 0;
 
   // 4a. seed + first row of each band, one segment at a time.  Windows
   // outside the image are not computed: bands starting below it are
   // skipped and the walk stops at the last column inside it.
   const int cols_in = min(tw, a.w - tx0);
-  for (int s = 0; s < segs && !failed; ++s) {
+  for (int s = 0; s < segs; ++s) {
     const int brow = (wid * segs + s) * R;
     if (ty0 + brow >= a.h) break;
     const int cy = brow - a.dy_min;
-    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, a, om, I, hist, rsp, blocks);
+    int ep = 0, ec = 0;
+    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, hshift, a, om, I, hist, rsp, blocks,
+                                       ep, ec);
     ++seeds;
-    if (BR && ms < mlo) {
-      failed = true;
-      break;
+    int hp = ms, hc = k;   // wave-uniform pivot and count
+    if (BR && ms < 0) {
+      hp = ep;
+      hc = ec;
     }
     m = set_lane(ms, s * tw, m);
+    vp = set_lane(hp, s * tw, vp);
+    vc = set_lane(hc, s * tw, vc);
+    if (BR) miss = set_lane(ms < 0, s * tw, miss);
     for (int c = 1; c < cols_in; ++c) {
       const int cxp = c - 1 - a.dx_min;
-      const uint32_t pre_up = om[min(ms + lane, Tv - 1)];
-      const uint32_t pre_dn = om[max(ms - 64 + lane, 0)];
-      const int cnt_new = k + hstep_delta(cxp, cy, ms, a, I, hrow);
-      ms = scan_core<SHAPE>(ms, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
-                            om, rsp, blocks, pre_up, pre_dn);
-      if (BR && ms < mlo) {
-        failed = true;
-        break;
+      const uint32_t pre_up = om[min(hp + lane, Tv - 1)];
+      const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
+      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow);
+      int c_end = 0;
+      ms = scan_core<SHAPE>(hp, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
+                            om, rsp, blocks, pre_up, pre_dn, c_end);
+      if (!BR || ms >= 0) {
+        hp = ms;
+        hc = k;
+      } else {
+        hp = cnt_new <= k ? Tv : 1;
+        hc = c_end;
       }
       m = set_lane(ms, s * tw + c, m);
+      vp = set_lane(hp, s * tw + c, vp);
+      vc = set_lane(hc, s * tw + c, vc);
+      if (BR) miss = set_lane(ms < 0, s * tw + c, miss);
     }
   }
   if (a.counters) seed_taps = seeds;  // taps per seed added on the host
   const long long clk2 = a.counters ? (long long)clock64() : 0;
-  if (!failed) {
+  {
     const int gx = tx0 + col, gy = ty0 + row0;
-    if (lane < segs * tw && col < cols_in && gy < a.h) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    const bool own = lane < segs * tw && col < cols_in && gy < a.h;
+    if (own && !miss) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    if (BR) push_misses(a, own && miss, gx, gy);
   }
 
   // 4b. vertical sweep down each band (lanes whose column or row is
@@ -602,7 +713,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
   const bool in_cols = lane < segs * tw && col < cols_in;
   const int rows_in = a.h - (ty0 + row0);   // rows of this lane's band inside the image
   const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, a.h - ty0 - wid * segs * R)));
-  for (int r = 1; r < r_end && !failed; ++r) {
+  for (int r = 1; r < r_end; ++r) {
     const bool lane_active = in_cols && r < rows_in;
     const int cy_prev = row0 + r - 1 - a.dy_min;
     const int lbase = cy_prev * a.pitch + cxl;
@@ -611,34 +722,50 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
 #pragma unroll 4
       for (int j = 0; j < a.ncols; ++j) {
         const int4 o = vtab[j];
-        delta += (int)(I[lbase + o.x] < m) - (int)(I[lbase + o.y] < m);
+        delta += (int)(I[lbase + o.x] < vp) - (int)(I[lbase + o.y] < vp);
       }
     }
-    int pl = m, cl = k + delta;
-    int mnew = m;
+    int pl = vp, cl = vc + delta;
+    int mnew = m, esc = 0;
     const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
-    if (lane_active)
+    if (lane_active) {
       mnew = lane_select<SHAPE>(pl, cl, k, cxy, kLaneBudget, Tv, a, om, rsp, groups);
-    uint64_t left = __ballot(lane_active && mnew < 0);
+      if (BR && mnew < 0 && (pl <= 0 || pl >= Tv)) {
+        // walked off an end of the bracket: a miss
+        esc = 1;
+        if (pl <= 0) pl = 1;
+      }
+    }
+    uint64_t left = __ballot(lane_active && mnew < 0 && !esc);
     while (left) {
       const int L = __ffsll((unsigned long long)left) - 1;
       left &= left - 1;
       const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
-      const int mL = scan_select<KT, SHAPE>(__builtin_amdgcn_readlane(pl, L),
-                                            __builtin_amdgcn_readlane(cl, L), k, cxyL & 0xffff,
-                                            cxyL >> 16, Tv, a, om, rsp, blocks);
+      const int plL = __builtin_amdgcn_readlane(pl, L), clL = __builtin_amdgcn_readlane(cl, L);
+      int c_end = 0;
+      const int mL = scan_select<KT, SHAPE>(plL, clL, k, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
+                                            rsp, blocks, c_end);
       mnew = set_lane(mL, L, mnew);
+      if (BR && mL < 0) {
+        pl = set_lane(clL <= k ? Tv : 1, L, pl);
+        cl = set_lane(c_end, L, cl);
+        esc = set_lane(1, L, esc);
+      }
     }
-    if (BR && __ballot(lane_active && mnew < mlo)) {
-      failed = true;
-      break;
+    if (lane_active) {
+      if (!BR || !esc) {
+        m = mnew;
+        vp = mnew;
+        vc = k;
+      } else {
+        vp = pl;
+        vc = cl;
+      }
     }
-    m = mnew;
     const int gx = tx0 + col, gy = ty0 + row0 + r;
-    if (lane_active) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    if (lane_active && !esc) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    if (BR) push_misses(a, lane_active && esc, gx, gy);
   }
-  if (BR && failed && lane == 0) atomicOr(&a.tile_fail[tile], 1);
-
   if (a.counters && lane == 0) {
     const long long clk3 = (long long)clock64();
     atomicAdd(&a.counters[CNT_BLOCKS], (unsigned long long)blocks);
@@ -654,6 +781,7 @@ __device__ __forceinline__ void tile_body(const ImageDesc& a, int tile, unsigned
     for (int d = 32; d >= 1; d >>= 1) gsum += __shfl_xor(gsum, d, 64);
     if (lane == 0) atomicAdd(&a.counters[CNT_GROUPS], gsum);
   }
+  return false;
 }
 
 }  // namespace mf
