@@ -139,7 +139,7 @@ int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, 
                             hipStream_t stream);
 
 /* Learned filter: the network proposes the brackets (union of a tile's
- * cells, widened by the margin; a bracket wider than half the value range
+ * cells, widened by the margin; a bracket wider than 0.3 of the value range
  * is dropped and the tile computed by the plain engine), then as
  * median_filter_bracketed. */
 int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, int dtype,

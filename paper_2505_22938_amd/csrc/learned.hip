@@ -49,43 +49,31 @@ __global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a, 
   if (threadIdx.x == 0) tile_fail[tile] = bad ? 1 : 0;
 }
 
-// The plain pass recomputes flagged tiles in sub-tiles (the bracketed tile
-// split rx x ry ways), so a failed tile's work spreads over several
-// workgroups instead of one tile time at the end.  Sub-tile `sub` of the
-// plain plan lies in bracketed tile `parent`.
-__device__ __forceinline__ int parent_tile(const ImageDesc& f, int sub, int parent_tiles_x, int rx,
-                                           int ry) {
-  return ((sub / f.tiles_x) / ry) * parent_tiles_x + (sub % f.tiles_x) / rx;
-}
-
-// Plain pass over the flagged tiles, LDS variant: one workgroup per sub-tile.
+// Plain pass over the flagged tiles, LDS variant: one workgroup per tile.
 template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc f, const int* tile_fail,
-                                                               int parent_tiles_x, int rx, int ry,
                                                                unsigned long long* fail_px) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int sub = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile_fail[parent_tile(f, sub, parent_tiles_x, rx, ry)] == 0) return;   // uniform
-  tile_body<KT, SHAPE, IMAX, false, false>(f, sub, smem, nullptr);
-  if (threadIdx.x == 0) count_fallback(f, sub, fail_px);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile_fail[tile] == 0) return;   // uniform per workgroup
+  tile_body<KT, SHAPE, IMAX, false, false>(f, tile, smem, nullptr);
+  if (threadIdx.x == 0) count_fallback(f, tile, fail_px);
 }
 
 // Plain pass over the flagged tiles, global-scratch variant: a persistent
-// grid over the sub-tiles, one scratch slot per workgroup.
+// grid, one scratch slot per workgroup.
 template <int KT, int SHAPE>
 __global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
                                                                   const int* tile_fail,
-                                                                  int parent_tiles_x, int rx,
-                                                                  int ry,
                                                                   unsigned long long* fail_px) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* slot = f.scratch + (long long)blockIdx.x * f.slot_bytes;
-  const int nsub = f.tiles_x * f.tiles_y;
-  for (int v = blockIdx.x; v < nsub; v += gridDim.x) {
-    const int sub = xcd_tile(v, nsub);
-    if (tile_fail[parent_tile(f, sub, parent_tiles_x, rx, ry)] == 0) continue;   // uniform
-    tile_body<KT, SHAPE, 1, true>(f, sub, smem, slot);
-    if (threadIdx.x == 0) count_fallback(f, sub, fail_px);
+  const int ntiles = f.tiles_x * f.tiles_y;
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const int tile = xcd_tile(v, ntiles);
+    if (tile_fail[tile] == 0) continue;   // uniform per workgroup
+    tile_body<KT, SHAPE, 1, true>(f, tile, smem, slot);
+    if (threadIdx.x == 0) count_fallback(f, tile, fail_px);
     __syncthreads();
   }
 }
@@ -176,8 +164,20 @@ __global__ __launch_bounds__(256) void bracket_kernel(const float* __restrict__ 
   const int tile = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
   if (tile >= ntiles) return;   // uniform per wave
   const int tx0 = (tile % tiles_x) * tw, ty0 = (tile / tiles_x) * th;
-  const int c0 = tx0 / 8, c1 = min(wc, (tx0 + tw + 7) / 8);
-  const int r0 = ty0 / 8, r1 = min(hc, (ty0 + th + 7) / 8);
+  int c0 = tx0 / 8, c1 = min(wc, (tx0 + tw + 7) / 8);
+  int r0 = ty0 / 8, r1 = min(hc, (ty0 + th + 7) / 8);
+  // cells within kEdge of the image border see the convolutions' zero
+  // padding and predict poorly; a tile with other cells ignores them (a
+  // border pixel whose median then escapes is recomputed exactly)
+  constexpr int kEdge = 4;
+  const int ic0 = max(c0, kEdge), ic1 = min(c1, wc - kEdge);
+  const int ir0 = max(r0, kEdge), ir1 = min(r1, hc - kEdge);
+  if (ic0 < ic1 && ir0 < ir1) {
+    c0 = ic0;
+    c1 = ic1;
+    r0 = ir0;
+    r1 = ir1;
+  }
   const int ncx = c1 - c0, ncell = ncx * (r1 - r0);
   float lo = 3.4e38f, hi = -3.4e38f;
   for (int i = lane; i < ncell; i += 64) {
@@ -194,9 +194,9 @@ __global__ __launch_bounds__(256) void bracket_kernel(const float* __restrict__ 
     float L = floorf((lo - margin) * maxval), H = ceilf((hi + margin) * maxval);
     L = fminf(fmaxf(L, 0.f), maxval);
     H = fminf(fmaxf(H, 0.f), maxval);
-    // empty, NaN, or wider than half the value range: no bracket (lo > hi),
+    // empty, NaN, or wider than 0.3 of the value range: no bracket (lo > hi),
     // the tile goes straight to the plain pass
-    if (!(L <= H) || H - L > 0.5f * maxval) br[tile] = make_uint2(1u, 0u);
+    if (!(L <= H) || H - L > 0.3f * maxval) br[tile] = make_uint2(1u, 0u);
     else br[tile] = make_uint2((unsigned)L, (unsigned)H);
   }
 }
@@ -337,7 +337,7 @@ int net_forward(mf_learned* n, const void* img, int w, int h, size_t stride, int
 }
 
 using BrKernel = void (*)(mf::ImageDesc, int*);
-using FbKernel = void (*)(mf::ImageDesc, const int*, int, int, int, unsigned long long*);
+using FbKernel = void (*)(mf::ImageDesc, const int*, unsigned long long*);
 
 template <int KT, int SHAPE>
 void pick(const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
@@ -354,15 +354,14 @@ void pick(const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
   }
 }
 
-// Tile plans of the learned path: the bracketed layout `br` on the tile
-// shape the plain filter would use, and the plain layout `fb` (LDS if it
-// fits, else global scratch) of the fallback pass, on the largest sub-tile
-// shape (halved width and/or height) that is valid, rx x ry sub-tiles per
-// bracketed tile.
+// Tile plans of the learned path, both on the tile shape the plain filter
+// would use: the bracketed layout `br`, and the plain layout `fb` (LDS if it
+// fits, else global scratch) of the pass over tiles with too many
+// in-bracket pixels.
 struct LearnedPlan {
   mf::ImageDesc br, fb;
   mf::DeviceInfo di;
-  int dev, rx, ry;
+  int dev;
 };
 
 int learned_plan(int dtype, const mf_footprint* fp, LearnedPlan* lp) {
@@ -373,20 +372,11 @@ int learned_plan(int dtype, const mf_footprint* fp, LearnedPlan* lp) {
   if ((rc = mf::choose_plan(dtype, fp, lp->di.lds_max, 33, &base))) return rc;
   if ((rc = mf::make_plan_br(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->br)))
     return rc;
-  const int tw = base.tw, th = base.th;
-  const int shapes[4][2] = {{tw / 2, th / 2}, {tw, th / 2}, {tw / 2, th}, {tw, th}};
-  for (const auto& sh : shapes) {
-    const int sw = sh[0], shh = sh[1];
-    if (sw < 1 || shh < 1 || tw % sw || th % shh) continue;
-    mf::ImageDesc f{};
-    if (mf::make_plan(dtype, fp, lp->di.lds_max, sw, shh, &f) != MF_OK || f.imax > 33)
-      if (mf::make_plan_gs(dtype, fp, lp->di.lds_max, sw, shh, &f) != MF_OK) continue;
-    lp->fb = f;
-    lp->rx = tw / sw;
-    lp->ry = th / shh;
-    return MF_OK;
-  }
-  return MF_ERR_UNSUPPORTED;
+  if (mf::make_plan(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->fb) != MF_OK ||
+      lp->fb.imax > 33)
+    if ((rc = mf::make_plan_gs(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->fb)))
+      return rc;
+  return MF_OK;
 }
 
 // Bracketed filter with per-tile brackets in `br` (the fallback count
@@ -416,11 +406,10 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
     if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(f, &bk, &fk);
     else pick<mf::KEY_U16, mf::SHAPE_SPANS>(f, &bk, &fk);
   }
-  const long long nsub = (long long)f.tiles_x * f.tiles_y;
-  long long fgrid = nsub;
+  long long fgrid = ntiles;
   if (f.gs) {
     const int occ = std::max(1, std::min(2, lp.di.lds_max / std::max(1, f.lds_bytes)));
-    fgrid = std::min<long long>(nsub, (long long)lp.di.cus * occ);
+    fgrid = std::min<long long>(ntiles, (long long)lp.di.cus * occ);
     void* scr = nullptr;
     if ((rc = mf::get_scratch(lp.dev, s, (size_t)fgrid * (size_t)f.slot_bytes, &scr))) return rc;
     f.scratch = static_cast<unsigned char*>(scr);
@@ -432,7 +421,7 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
   hipLaunchKernelGGL(bk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a,
                      n->tile_fail);
   hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
-                     (const int*)n->tile_fail, a.tiles_x, lp.rx, lp.ry, n->fail_px);
+                     (const int*)n->tile_fail, n->fail_px);
   const long long pgrid = std::max(1, lp.di.cus) * 4LL;
   if (dtype == MF_U8)
     hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,

@@ -41,14 +41,21 @@ def tile_margins(cells_out: np.ndarray, median: np.ndarray, tw: int, th: int) ->
     """Per tile: the widening (in full-range units) its cell-union bracket
     needs to contain every median of the tile."""
     h, w = median.shape
+    hc, wc = cells_out.shape[:2]
     lo = np.minimum(cells_out[..., 0], cells_out[..., 1])
     hi = np.maximum(cells_out[..., 0], cells_out[..., 1])
+    edge = 4   # as the library's bracket kernel: border cells are ignored when possible
     out = []
     for ty in range(0, h, th):
         for tx in range(0, w, tw):
             m = median[ty:ty + th, tx:tx + tw].astype(np.float64) / 65535.0
-            cl = lo[ty // 8:(ty + th + 7) // 8, tx // 8:(tx + tw + 7) // 8]
-            ch = hi[ty // 8:(ty + th + 7) // 8, tx // 8:(tx + tw + 7) // 8]
+            r0, r1 = ty // 8, min(hc, (ty + th + 7) // 8)
+            c0, c1 = tx // 8, min(wc, (tx + tw + 7) // 8)
+            ir0, ir1, ic0, ic1 = max(r0, edge), min(r1, hc - edge), max(c0, edge), min(c1, wc - edge)
+            if ir0 < ir1 and ic0 < ic1:
+                r0, r1, c0, c1 = ir0, ir1, ic0, ic1
+            cl = lo[r0:r1, c0:c1]
+            ch = hi[r0:r1, c0:c1]
             need = max(cl.min() - m.min(), m.max() - ch.max(), 0.0)
             out.append(need)
     return np.array(out)
