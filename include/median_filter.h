@@ -182,18 +182,19 @@ int median_filter_batched(const mf_image_desc* descs, int n, hipStream_t stream)
  * ------------------------------------------------------------------------ */
 int mf_set_tile_override(int tile_w, int tile_h);
 
-/* Work counters of the plain filter, for the benchmark's work model.
- * enable = 1: allocate (once) and zero eight device counters that later
- * calls accumulate into: [0] wave-cooperative omnigram blocks scanned
- * (64 ordinals each), [1] seed windows solved, [2] [3] [4] shader clocks summed over waves spent in load+sort,
- * in seeds and first band rows, and in vertical sweeps, [5] number of
- * waves summed, [6] lane-parallel 8-ordinal groups tested, [7] box pixels
- * ranked by the ordinal transforms (the learned and bracketed filters count
- * into the same counters).  enable = 0: stop counting and free
- * them.  enable = -1: copy the eight counters to the host array `out8`
- * (synchronous).  Not thread-safe against concurrent filter calls.
- * Counting adds a few scalar instructions per block. */
-int mf_work_counters(int enable, unsigned long long* out8);
+/* Work counters of the tile engine, for the benchmark's work model.
+ * enable = 1: allocate (once) and zero ten device counters that later calls
+ * accumulate into: [0] wave-cooperative omnigram blocks scanned (64
+ * ordinals each), [1] seed windows solved, [2] [3] [4] shader clocks summed
+ * over waves spent in load + sort, in seeds and first band rows, and in
+ * vertical sweeps, [5] number of waves summed, [6] lane-parallel 8-ordinal
+ * groups tested, [7] box pixels ranked by the ordinal transforms, [8]
+ * shader clocks in seed solves (part of [3]), [9] reserved (0).  The
+ * learned and bracketed filters count into the same counters.  enable = 0:
+ * stop counting and free them.  enable = -1: copy the ten counters to the
+ * host array `out10` (synchronous).  Not thread-safe against concurrent
+ * filter calls.  Counting adds a few scalar instructions per block. */
+int mf_work_counters(int enable, unsigned long long* out10);
 
 /* ------------------------------------------------------------------------
  * Autotuner (not in the paper).  Times every valid tile shape of the plain

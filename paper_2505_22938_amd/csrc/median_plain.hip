@@ -196,8 +196,8 @@ int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, 
   return MF_OK;
 }
 
-int mf_work_counters(int enable, unsigned long long* out8) {
-  if (enable < 0) return out8 ? mf::read_counters(out8) : MF_ERR_INVALID_ARG;
+int mf_work_counters(int enable, unsigned long long* out10) {
+  if (enable < 0) return out10 ? mf::read_counters(out10) : MF_ERR_INVALID_ARG;
   return mf::set_counters(enable);
 }
 

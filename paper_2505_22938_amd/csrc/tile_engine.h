@@ -49,13 +49,18 @@ enum {
   CNT_WAVES = 5,       // waves that reported clocks
   CNT_GROUPS = 6,      // lane-parallel 8-ordinal groups tested (summed over lanes)
   CNT_SORTED = 7,      // box pixels ranked by the ordinal transform (summed over tiles)
-  CNT_SLOTS = 8
+  CNT_CYC_SEED = 8,    // shader clocks per wave spent in seed solves (part of CNT_CYC_ROW)
+  CNT_SLOTS = 10
 };
 
 // Set lane L of a per-lane value to a wave-uniform value.
 __device__ __forceinline__ int set_lane(int v, int L, int old) {
   return (int)(threadIdx.x & 63) == L ? v : old;
 }
+
+// 64-lane mask of a per-lane condition (straight from the compare, no
+// detour through an integer predicate).
+__device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -65,6 +70,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 
 typedef short s2v __attribute__((ext_vector_type(2)));
+
+// d.x * d.x + d.y * d.y + c as one VOP3P dot product (the addend from a
+// scalar register, no accumulator copy).
+__device__ __forceinline__ int dot2_sq_add(s2v d, int c) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(r) : "v"(d), "s"(c));
+  return r;
+}
 
 // Window membership of an omnigram entry (paper, Eq. 2/3).  `w` holds the
 // entry's box location in its low 16 bits (x: bits 0-7, y: bits 8-15);
@@ -76,13 +89,44 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
                                               int nrows, const short2* rsp) {
   const uint32_t pk = __builtin_amdgcn_perm(0u, w, 0x0c010c00u);
   const s2v d = __builtin_bit_cast(s2v, pk) - __builtin_bit_cast(s2v, cxy);
-  if (SHAPE == SHAPE_DISC) return __builtin_amdgcn_sdot2(d, d, 0, false) <= limit;
+  // dx^2 + dy^2 - (limit + 1) < 0: the threshold rides in the dot product's addend
+  if (SHAPE == SHAPE_DISC) return dot2_sq_add(d, -limit - 1) < 0;
   const int r = (int)d.y - dy_min;
   if ((unsigned)r >= (unsigned)nrows) return false;
   const short2 s = rsp[r];
   return (int)d.x >= (int)s.x && (int)d.x <= (int)s.y;
 }
 
+
+// Membership of the eight omnigram entries in g (two per word), bit j for
+// entry j.  Disc: per entry one byte permute, one packed subtract and one
+// dot product whose sign bit is shifted into the mask (v_alignbit).
+template <int SHAPE>
+__device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, const ImageDesc& a,
+                                               const short2* rsp) {
+  const uint32_t wv[4] = {g.x, g.y, g.z, g.w};
+  if constexpr (SHAPE == SHAPE_DISC) {
+    const s2v c = __builtin_bit_cast(s2v, cxy);
+    const int negl = -a.limit - 1;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+      const uint32_t pk = __builtin_amdgcn_perm(0u, wv[j >> 1], (j & 1) ? 0x0c030c02u : 0x0c010c00u);
+      const s2v d = __builtin_bit_cast(s2v, pk) - c;
+      const int r = dot2_sq_add(d, negl);
+      acc = __builtin_amdgcn_alignbit(acc, (uint32_t)r, 31u);
+    }
+    return acc;
+  } else {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t e = (j & 1) ? (wv[j >> 1] >> 16) : wv[j >> 1];
+      bits |= (uint32_t)member_packed<SHAPE>(e, cxy, a.limit, a.dy_min, a.nrows, rsp) << j;
+    }
+    return bits;
+  }
+}
 
 // Rank selection for one window (wave-uniform arguments): given a pivot
 // ordinal p and the number c of window members with ordinal < p, return the
@@ -113,13 +157,13 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       const uint32_t nxt = om[min(max(b + 64 + lane, 0), T - 1)];
       const bool in = b + lane < T &&
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
-      const uint64_t mask = __ballot(in);
+      const uint64_t mask = wave_ballot(in);
       const int pc = __popcll(mask);
       ++blocks;
       if (need < pc) {
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        const uint64_t hit = __ballot(in && below == need);
+        const uint64_t hit = wave_ballot(in && below == need);
         return b + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
@@ -135,14 +179,14 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       const int v = b - 64 + lane;
       const bool in = v >= 0 && v < T &&
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
-      const uint64_t mask = __ballot(in);
+      const uint64_t mask = wave_ballot(in);
       const int pc = __popcll(mask);
       ++blocks;
       if (need <= pc) {
         const int idx = pc - need;
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        const uint64_t hit = __ballot(in && below == idx);
+        const uint64_t hit = wave_ballot(in && below == idx);
         return b - 64 + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
@@ -182,31 +226,23 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
   int q = up ? (p & ~7) : ((p - 1) & ~7);
   int below = c;   // members below the frontier
   int m = -1, it = 0;
+  uint32_t bits = 0;
   // first (partial) group: only ordinals in [p, T) (up) or [0, p) (down);
   // p > 0 whenever the walk goes down, so q >= 0
   {
     const uint4 g = *reinterpret_cast<const uint4*>(om + max(q, 0));
-    const uint32_t e[8] = {g.x, g.x >> 16, g.y, g.y >> 16, g.z, g.z >> 16, g.w, g.w >> 16};
-    uint32_t bits = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool in_range = up ? (q + j >= p && q + j < T) : (q + j < p);
-      bits |= (uint32_t)(in_range &&
-                         member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp)) << j;
+    uint32_t range;
+    if (up) {
+      const int hi = T - q;   // entries j < hi are below T
+      range = (0xffu << (p - q)) & (hi >= 8 ? 0xffu : ((1u << max(hi, 0)) - 1u));
+    } else {
+      range = (1u << (p - q)) - 1u;
     }
+    bits = group_mask<SHAPE>(g, cxy, a, rsp) & range;
     const int cnt = __builtin_popcount(bits);
     ++it;
     if (need < cnt) {
-      int n = need, jsel = 0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int jj = up ? t : 7 - t;
-        if ((bits >> jj) & 1u) {
-          if (n == 0) jsel = jj;
-          --n;
-        }
-      }
-      m = q + jsel;
+      m = q;   // selection below
     } else {
       need -= cnt;
       below += up ? cnt : -cnt;
@@ -216,32 +252,30 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
   // full groups: count members only
   while (m < 0 && (up ? q < T : q >= 0) && it < budget) {
     const uint4 g = *reinterpret_cast<const uint4*>(om + q);
-    const uint32_t e[8] = {g.x, g.x >> 16, g.y, g.y >> 16, g.z, g.z >> 16, g.w, g.w >> 16};
-    int cnt = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      cnt += (int)member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp);
+    bits = group_mask<SHAPE>(g, cxy, a, rsp);
+    const int cnt = __builtin_popcount(bits);
     ++it;
     if (need < cnt) {
-      uint32_t bits = 0;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        bits |= (uint32_t)member_packed<SHAPE>(e[j], cxy, a.limit, a.dy_min, a.nrows, rsp) << j;
-      int n = need, jsel = 0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int jj = up ? t : 7 - t;
-        if ((bits >> jj) & 1u) {
-          if (n == 0) jsel = jj;
-          --n;
-        }
-      }
-      m = q + jsel;
+      m = q;
       break;
     }
     need -= cnt;
     below += up ? cnt : -cnt;
     q += up ? 8 : -8;
+  }
+  if (m >= 0) {
+    // the need-th member of the group (from the bottom going up, from the
+    // top going down)
+    int n = need, jsel = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int jj = up ? t : 7 - t;
+      if ((bits >> jj) & 1u) {
+        if (n == 0) jsel = jj;
+        --n;
+      }
+    }
+    m = q + jsel;
   }
   groups += it;
   if (m < 0) {
@@ -310,7 +344,7 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, con
     }
     cum += h[j];
   }
-  const uint64_t who = __ballot(bin >= 0);
+  const uint64_t who = wave_ballot(bin >= 0);
   if (BR && who == 0) {             // median above the bracket
     esc_p = T;
     esc_c = zeros + __builtin_amdgcn_readlane((int)cum, 63);
@@ -330,11 +364,17 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, con
 // further rounds of 128 rows for taller windows); hrow[i] = (entering
 // offset, leaving offset) of row i.
 __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDesc& a,
-                                           const uint16_t* I, const int2* hrow) {
+                                           const uint16_t* I, const int2* hrow,
+                                           const int4& own) {
   const int lane = threadIdx.x & 63;
   const int base = cy * a.pitch + cx;
-  int delta = 0;
-  for (int i0 = 0; i0 < a.nrows; i0 += 128) {
+  // rows lane and lane + 64: offsets held in registers (own); a row beyond
+  // the footprint reads the same entry twice and cancels
+  int delta = __popcll(wave_ballot(I[base + own.x] < p)) -
+              __popcll(wave_ballot(I[base + own.y] < p)) +
+              __popcll(wave_ballot(I[base + own.z] < p)) -
+              __popcll(wave_ballot(I[base + own.w] < p));
+  for (int i0 = 128; i0 < a.nrows; i0 += 128) {
     const int i1 = i0 + lane, i2 = i0 + 64 + lane;
     bool e1 = false, l1 = false, e2 = false, l2 = false;
     if (i1 < a.nrows) {
@@ -347,8 +387,8 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDes
       e2 = I[base + o.x] < p;
       l2 = I[base + o.y] < p;
     }
-    delta += __popcll(__ballot(e1)) + __popcll(__ballot(e2)) - __popcll(__ballot(l1)) -
-             __popcll(__ballot(l2));
+    delta += __popcll(wave_ballot(e1)) + __popcll(wave_ballot(e2)) -
+             __popcll(wave_ballot(l1)) - __popcll(wave_ballot(l2));
   }
   return delta;
 }
@@ -367,7 +407,7 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 // Bracketed tiles: append the flagged output pixels of the wave (index
 // y * w + x) to the miss list.  Call with the whole wave.
 __device__ __forceinline__ void push_misses(const ImageDesc& a, bool missed, int gx, int gy) {
-  const uint64_t mb = __ballot(missed);
+  const uint64_t mb = wave_ballot(missed);
   if (mb == 0) return;
   const int lane = threadIdx.x & 63;
   uint32_t base = 0;
@@ -510,7 +550,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
           below_bits |= (uint64_t)below << (c0 + j);
           above_bits |= (uint64_t)above << (c0 + j);
         }
-        bal[j] = __ballot(valid[j] && !below && !above);
+        bal[j] = wave_ballot(valid[j] && !below && !above);
         total += (uint32_t)__popcll(bal[j]);
       }
       uint32_t base = 0;
@@ -644,6 +684,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   }
   uint32_t* hist = hist_all + wid * 128;
   int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
+  long long seed_clk = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;
   const int seg = lane / tw, col = lane - seg * tw;
   const int band = wid * segs + seg;
@@ -661,13 +702,24 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   // outside the image are not computed: bands starting below it are
   // skipped and the walk stops at the last column inside it.
   const int cols_in = min(tw, a.w - tx0);
+  int4 hown = make_int4(0, 0, 0, 0);   // this lane's rows of hrow (lane, lane + 64)
+  if (lane < a.nrows) {
+    hown.x = hrow[lane].x;
+    hown.y = hrow[lane].y;
+  }
+  if (lane + 64 < a.nrows) {
+    hown.z = hrow[lane + 64].x;
+    hown.w = hrow[lane + 64].y;
+  }
   for (int s = 0; s < segs; ++s) {
     const int brow = (wid * segs + s) * R;
     if (ty0 + brow >= a.h) break;
     const int cy = brow - a.dy_min;
     int ep = 0, ec = 0;
+    const long long cs0 = a.counters ? (long long)clock64() : 0;
     int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, hshift, a, om, I, hist, rsp, blocks,
                                        ep, ec);
+    if (a.counters) seed_clk += (long long)clock64() - cs0;
     ++seeds;
     int hp = ms, hc = k;   // wave-uniform pivot and count
     if (BR && ms < 0) {
@@ -682,7 +734,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
       const int cxp = c - 1 - a.dx_min;
       const uint32_t pre_up = om[min(hp + lane, Tv - 1)];
       const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
-      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow);
+      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow, hown);
       int c_end = 0;
       ms = scan_core<SHAPE>(hp, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
                             om, rsp, blocks, pre_up, pre_dn, c_end);
@@ -736,7 +788,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
         if (pl <= 0) pl = 1;
       }
     }
-    uint64_t left = __ballot(lane_active && mnew < 0 && !esc);
+    uint64_t left = wave_ballot(lane_active && mnew < 0 && !esc);
     while (left) {
       const int L = __ffsll((unsigned long long)left) - 1;
       left &= left - 1;
@@ -774,6 +826,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
     atomicAdd(&a.counters[CNT_CYC_ROW], (unsigned long long)(clk2 - clk1));
     atomicAdd(&a.counters[CNT_CYC_SWEEP], (unsigned long long)(clk3 - clk2));
     atomicAdd(&a.counters[CNT_WAVES], 1ull);
+    atomicAdd(&a.counters[CNT_CYC_SEED], (unsigned long long)seed_clk);
   }
   if (a.counters) {
     // lane-parallel groups differ per lane: sum over the wave
