@@ -32,10 +32,9 @@ int g_tile_w = 0, g_tile_h = 0;
 
 // Band layout shared by both variants; fills geometry fields.
 int band_geometry(const mf_footprint* fp, int tw, int th, ImageDesc* d) {
-  if (tw < 1 || tw > 64 || 64 % tw) return MF_ERR_UNSUPPORTED;
-  const int segs = 64 / tw;
-  if (th < 1 || th % (kWaves * segs)) return MF_ERR_UNSUPPORTED;
-  const int R = th / (kWaves * segs);
+  if (tw < 1 || tw > 64 || th < 1) return MF_ERR_UNSUPPORTED;
+  const int segs = 64 / tw;                                // bands per wave
+  const int R = (th + kWaves * segs - 1) / (kWaves * segs);   // rows per band
   const int bw = tw + fp->dx_max - fp->dx_min, bh = th + fp->dy_max - fp->dy_min;
   if (bw > 255 || bh > 256) return MF_ERR_UNSUPPORTED;
   const int T = bw * bh;
@@ -199,6 +198,37 @@ static int plan_shape(int dtype, const mf_footprint* fp, int lds_max, int imax_c
   return make_plan_gs(dtype, fp, lds_max, tw, th, d);
 }
 
+// Global-scratch plans (large windows): the tile shape with the least box
+// amplification T / (tw * th) among shapes that keep at least 3/4 of the
+// lanes and half of the waves busy in the band phase.  Widths need not
+// divide 64 (a wave then owns one band and some lanes sit out).
+int best_gs_plan(int dtype, const mf_footprint* fp, int lds_max, ImageDesc* d) {
+  static const int tws[] = {64, 56, 54, 48, 32, 16};
+  static const int ths[] = {128, 112, 96, 80, 64, 56, 54, 48, 32, 16};
+  double best = 1e300;
+  ImageDesc pick{};
+  bool found = false;
+  for (int w : tws) {
+    const int segs = 64 / w;
+    if (w * segs < 48) continue;
+    for (int h : ths) {
+      ImageDesc c{};
+      if (make_plan_gs(dtype, fp, lds_max, w, h, &c) != MF_OK) continue;
+      const int bands = (h + c.band_rows - 1) / c.band_rows;
+      if (bands * 2 < kWaves * segs && h > kWaves) continue;
+      const double amp = (double)c.T / ((double)w * h);
+      if (amp < best) {
+        best = amp;
+        pick = c;
+        found = true;
+      }
+    }
+  }
+  if (!found) return MF_ERR_UNSUPPORTED;
+  *d = pick;
+  return MF_OK;
+}
+
 int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d) {
   int tw = 0, th = 0;
   get_override(&tw, &th);
@@ -206,19 +236,27 @@ int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, Im
   if (tuned_shape(dtype, fp, &tw, &th) &&
       plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d) == MF_OK)
     return MF_OK;
+  // the first LDS shape that fits (widest, tallest first), unless a
+  // global-scratch shape re-reads far fewer box pixels per output pixel
+  // (small LDS tiles under large windows).  Measured crossover: the
+  // global-scratch plan wins once the LDS plan's amplification is about 1.8x
+  // as high for 8/16-bit keys, 2.5x for float keys (64-bit words, 8 passes)
   static const int tws[] = {64, 32, 16, 8};
+  ImageDesc gs{};
+  const bool have_gs = best_gs_plan(dtype, fp, lds_max, &gs) == MF_OK;
   for (int w : tws) {
     const int segs = 64 / w;
     for (int R = 8; R >= 1; R /= 2)
-      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK && d->imax <= imax_cap)
+      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK && d->imax <= imax_cap) {
+        const double amp = (double)d->T / ((double)d->tw * d->th);
+        const double amp_gs = have_gs ? (double)gs.T / ((double)gs.tw * gs.th) : 1e300;
+        if (amp > (dtype == MF_F32 ? 2.5 : 1.8) * amp_gs) *d = gs;
         return MF_OK;
+      }
   }
-  for (int w : tws) {
-    const int segs = 64 / w;
-    for (int R = 8; R >= 1; R /= 2)
-      if (make_plan_gs(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK) return MF_OK;
-  }
-  return MF_ERR_UNSUPPORTED;
+  if (!have_gs) return MF_ERR_UNSUPPORTED;
+  *d = gs;
+  return MF_OK;
 }
 
 std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int lds_max,

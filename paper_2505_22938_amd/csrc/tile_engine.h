@@ -9,9 +9,10 @@
 //           ordinal v): the reverse map C and the omnigram (Eq. 4)
 //   I       ordinal image, I(loc(v)) = v, 16-bit, row pitch chosen so rows
 //           start in different LDS banks
-//   bands   the tile is cut into bands of `band_rows` rows and each wave
-//           owns `segs` bands side by side (a band is tw <= 64 columns, one
-//           lane per column).  Per band:
+//   bands   the tile is cut into bands of `band_rows` rows (the last one
+//           may be shorter) and each wave owns `segs` = 64 / tw bands side
+//           by side (a band is tw <= 64 columns, one lane per column; lanes
+//           past segs * tw and bands past the tile sit out).  Per band:
 //             seed  the first window of the band's first row is solved
 //                   with a coarse histogram of its ordinals, refined by an
 //                   omnigram scan (paper: seeds solved from low-precision
@@ -713,7 +714,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   }
   for (int s = 0; s < segs; ++s) {
     const int brow = (wid * segs + s) * R;
-    if (ty0 + brow >= a.h) break;
+    if (brow >= a.th || ty0 + brow >= a.h) break;   // band below the tile or the image
     const int cy = brow - a.dy_min;
     int ep = 0, ec = 0;
     const long long cs0 = a.counters ? (long long)clock64() : 0;
@@ -755,7 +756,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   const long long clk2 = a.counters ? (long long)clock64() : 0;
   {
     const int gx = tx0 + col, gy = ty0 + row0;
-    const bool own = lane < segs * tw && col < cols_in && gy < a.h;
+    const bool own = lane < segs * tw && col < cols_in && row0 < a.th && gy < a.h;
     if (own && !miss) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
     if (BR) push_misses(a, own && miss, gx, gy);
   }
@@ -763,8 +764,9 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   // 4b. vertical sweep down each band (lanes whose column or row is
   // outside the image sit out)
   const bool in_cols = lane < segs * tw && col < cols_in;
-  const int rows_in = a.h - (ty0 + row0);   // rows of this lane's band inside the image
-  const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, a.h - ty0 - wid * segs * R)));
+  const int rows_lim = min(a.h - ty0, a.th);   // tile rows inside the image
+  const int rows_in = rows_lim - row0;          // rows of this lane's band inside both
+  const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, rows_lim - wid * segs * R)));
   for (int r = 1; r < r_end; ++r) {
     const bool lane_active = in_cols && r < rows_in;
     const int cy_prev = row0 + r - 1 - a.dy_min;
