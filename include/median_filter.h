@@ -174,11 +174,12 @@ int median_filter_batched(const mf_image_desc* descs, int n, hipStream_t stream)
 
 /* ------------------------------------------------------------------------
  * Tile-shape control, for measurement and tuning.  tile_w/tile_h are the
- * output tile size: tile_w in {8, 16, 32, 64} and tile_h a multiple of
- * 16 * (64 / tile_w) (16 waves, each owning 64/tile_w bands of equal
- * height).  A shape whose input box exceeds 256 pixels or the LDS makes
- * later calls return MF_ERR_UNSUPPORTED.  (0, 0) restores the automatic
- * choice.  Affects later calls from every thread.
+ * output tile size, 1..64 by 1..256 (each of the 16 waves owns 64/tile_w
+ * bands side by side, bands of ceil(tile_h / (16 * (64/tile_w))) rows, the
+ * last one possibly shorter).  A shape whose input box exceeds 255 x 256
+ * pixels, 65535 pixels or the LDS makes later calls return
+ * MF_ERR_UNSUPPORTED.  (0, 0) restores the automatic choice.  Affects later
+ * calls from every thread.
  * ------------------------------------------------------------------------ */
 int mf_set_tile_override(int tile_w, int tile_h);
 

@@ -433,9 +433,7 @@ int tune_cache_save(const char* path) {
 
 extern "C" int mf_set_tile_override(int tile_w, int tile_h) {
   if (tile_w < 0 || tile_h < 0 || (tile_w == 0) != (tile_h == 0)) return MF_ERR_INVALID_ARG;
-  if (tile_w && (tile_w > 64 || 64 % tile_w || tile_w < 8 || tile_h > 256 ||
-                 tile_h % (16 * (64 / tile_w))))
-    return MF_ERR_INVALID_ARG;
+  if (tile_w && (tile_w > 64 || tile_h > 256)) return MF_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lock(mf::g_override_mu);
   mf::g_tile_w = tile_w;
   mf::g_tile_h = tile_h;

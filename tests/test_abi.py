@@ -113,3 +113,26 @@ def test_query_plan_geometry():
         assert (p2["tile_w"], p2["box_w"]) == (32, 96)
     finally:
         mf.set_tile_override(0, 0)
+
+
+def test_tile_override_validation_and_general_shapes():
+    with pytest.raises(mf.MedianFilterError):
+        mf.set_tile_override(65, 16)
+    with pytest.raises(mf.MedianFilterError):
+        mf.set_tile_override(0, 16)
+    mf.set_tile_override(40, 24)
+    try:
+        p = mf.query_plan(1000, 1000, mf.MF_U16, mf.Footprint.disc(8))
+        assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (40, 24, 56, 40)
+    finally:
+        mf.set_tile_override(0, 0)
+
+
+def test_large_window_plans_minimise_amplification():
+    """Radius 100: the box of a 54x56 tile (254x256) is the largest that fits
+    the 8-bit box coordinates; small LDS tiles are not used for radius 48+."""
+    p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(100))
+    assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (54, 56, 254, 256)
+    for r in (48, 56, 64):
+        p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(r))
+        assert p["tile_w"] * p["tile_h"] >= 64 * 96, (r, p)

@@ -172,3 +172,37 @@ def test_natural_u16_4096_sampled(mf, oracle_mod, r):
     xs, ys = sample_points(4096, 4096, 4000, 17)
     exp = oracle_mod.filter_points(img, OF.disc(r), xs, ys, "clamp")
     assert_same(got[ys, xs], exp, f"4096 r={r}")
+
+
+@pytest.mark.parametrize("dtype,fpname,tile", [
+    ("u16", "disc8", (40, 24)),      # width not dividing 64, last band shorter
+    ("u8", "ellipse", (48, 20)),
+    ("f32", "hexagon", (24, 40)),    # two bands per wave, 16 lanes idle
+    ("u16", "triangle", (64, 20)),
+    ("u16", "disc3", (7, 9)),
+])
+def test_plain_general_tile_shapes(mf, oracle_mod, dtype, fpname, tile):
+    """Tile shapes outside the power-of-two grid (forced through the tile
+    override), on ragged images with both boundaries."""
+    mk, ofp = FOOTPRINTS[fpname]
+    img = make_img(dtype, 203, 117, 31)
+    mf.set_tile_override(*tile)
+    try:
+        for boundary in ("clamp", "mirror"):
+            assert_same(run(mf, img, mk(mf), boundary), oracle_mod.filter(img, ofp(), boundary),
+                        f"{dtype} {fpname} {tile} {boundary}")
+    finally:
+        mf.set_tile_override(0, 0)
+
+
+@pytest.mark.parametrize("tile", [(54, 56), (40, 36)])
+def test_plain_large_radius_odd_tiles(mf, oracle_mod, tile):
+    """Radius 100 on global-scratch plans with odd tile shapes (the default
+    54x56 and a smaller one)."""
+    img = workloads.natural_u16(300, 260, 32)
+    mf.set_tile_override(*tile)
+    try:
+        assert_same(run(mf, img, mf.Footprint.disc(100), "clamp"),
+                    oracle_mod.filter(img, OF.disc(100), "clamp"), f"r100 {tile}")
+    finally:
+        mf.set_tile_override(0, 0)
