@@ -273,6 +273,12 @@ std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int ld
         out.push_back(d);
     }
   }
+  ImageDesc g{};
+  if (best_gs_plan(dtype, fp, lds_max, &g) == MF_OK) {
+    bool seen = false;
+    for (const ImageDesc& c : out) seen = seen || (c.tw == g.tw && c.th == g.th && c.gs);
+    if (!seen) out.push_back(g);
+  }
   return out;
 }
 
