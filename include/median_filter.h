@@ -190,7 +190,8 @@ int mf_set_tile_override(int tile_w, int tile_h);
  * over waves spent in load + sort, in seeds and first band rows, and in
  * vertical sweeps, [5] number of waves summed, [6] lane-parallel 8-ordinal
  * groups tested, [7] box pixels ranked by the ordinal transforms, [8]
- * shader clocks in seed solves (part of [3]), [9] reserved (0).  The
+ * shader clocks in seed solves (part of [3]), [9] shader clocks from tile start
+ * to the box loaded (part of [2]; 0 for global-scratch tiles).  The
  * learned and bracketed filters count into the same counters.  enable = 0:
  * stop counting and free them.  enable = -1: copy the ten counters to the
  * host array `out10` (synchronous).  Not thread-safe against concurrent

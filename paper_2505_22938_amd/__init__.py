@@ -243,7 +243,7 @@ def set_tile_override(tile_w: int = 0, tile_h: int = 0):
 def work_counters(enable: int):
     """enable=1: start (and zero) the device work counters; 0: stop; -1: read
     them -> [blocks scanned, seeds, clk sort, clk rows, clk sweeps, waves, lane groups,
-    pixels ranked, clk seeds, 0]."""
+    pixels ranked, clk seeds, clk load]."""
     buf = (ctypes.c_ulonglong * 10)()
     _check("mf_work_counters", lib().mf_work_counters(int(enable),
                                                       ctypes.cast(buf, ctypes.c_void_p)))

@@ -41,11 +41,11 @@ __device__ __forceinline__ void count_fallback(const ImageDesc& a, int tile,
 
 // Bracketed tiles: one workgroup per tile; writes the tile's fail flag
 // (median outside the bracket, or more in-bracket pixels than fit).
-template <int KT, int SHAPE>
+template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a, int* tile_fail) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const bool bad = tile_body<KT, SHAPE, 1, false, true>(a, tile, smem, nullptr);
+  const bool bad = tile_body<KT, SHAPE, IMAX, false, true>(a, tile, smem, nullptr);
   if (threadIdx.x == 0) tile_fail[tile] = bad ? 1 : 0;
 }
 
@@ -82,15 +82,21 @@ __global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
 // selects the rank-k value of its window straight from the image by radix
 // selection on the value bits: a 256-bin histogram of the top byte finds
 // the byte holding rank k, then (16-bit) a histogram of the low byte among
-// the values with that top byte.  Adds the list length to fail_px.
+// the values with that top byte.  The window's values are read once, eight
+// footprint rows at a time (their loads in flight together), and kept in
+// LDS for the second histogram when they fit (kStage values per wave;
+// larger windows are read again).  Adds the list length to fail_px.
 template <int KT>
 __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
                                                               const unsigned int* miss,
                                                               const unsigned int* miss_count,
                                                               unsigned long long* fail_px) {
+  constexpr int kStage = 4096, kRows = 8;
   __shared__ uint32_t hist_s[4][256];
+  __shared__ uint16_t stage_s[4][kStage];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t* hist = hist_s[wid];
+  uint16_t* stage = stage_s[wid];
   const int n = (int)*miss_count;
   if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(fail_px, (unsigned long long)n);
   const int nwaves = (int)gridDim.x * 4;
@@ -100,21 +106,69 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
     const int y = (int)(idx / (uint32_t)f.w), x = (int)(idx - (uint32_t)y * (uint32_t)f.w);
     int target = f.rank;
     uint32_t prefix = 0;
+    bool staged = true;   // every value of the window is in `stage`
     for (int pass = 0; pass < kPasses; ++pass) {
       const int sh = (kPasses - 1 - pass) * 8;
       for (int b = lane; b < 256; b += 64) hist[b] = 0;
       wave_lds_sync();
-      for (int r = 0; r < f.nrows; ++r) {
-        const short2 sp = f.spans[r];
-        const long long rowoff = (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
-        for (int dx = sp.x + lane; dx <= sp.y; dx += 64) {
-          const int gx = remap(x + dx, f.w, f.boundary);
-          const uint32_t v = KT == KEY_U8
-                                 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
-                                 : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
-          if (pass == 1 && (v >> 8) != prefix) continue;
-          atomicAdd(&hist[(v >> sh) & 255u], 1u);
+      if (pass == 1 && staged) {
+        int pos = 0;
+        for (int r = 0; r < f.nrows; ++r) pos += f.spans[r].y - f.spans[r].x + 1;
+        for (int j = lane; j < pos; j += 64) {
+          const uint32_t v = stage[j];
+          if ((v >> 8) == prefix) atomicAdd(&hist[v & 255u], 1u);
         }
+      } else {
+        int base = 0;   // position of the current row's first value in `stage`
+        for (int r0 = 0; r0 < f.nrows; r0 += kRows) {
+          uint32_t v[kRows][2];
+          bool ok[kRows][2];
+          int rb[kRows];
+#pragma unroll
+          for (int j = 0; j < kRows; ++j) {
+            const int r = min(r0 + j, f.nrows - 1);
+            const short2 sp = f.spans[r];
+            rb[j] = base;
+            if (r0 + j < f.nrows) base += sp.y - sp.x + 1;
+            const long long rowoff =
+                (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int dx = sp.x + lane + 64 * q;
+              ok[j][q] = r0 + j < f.nrows && dx <= sp.y;
+              const int gx = remap(x + min(dx, (int)sp.y), f.w, f.boundary);
+              v[j][q] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
+                                     : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < kRows; ++j)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              if (ok[j][q]) {
+                const int pos = rb[j] + lane + 64 * q;
+                if (pass == 0 && pos < kStage) stage[pos] = (uint16_t)v[j][q];
+                if (pass == 0 || (v[j][q] >> 8) == prefix)
+                  atomicAdd(&hist[(v[j][q] >> sh) & 255u], 1u);
+              }
+          // rows wider than 128 taps: the rest one load at a time
+          for (int j = 0; j < kRows && r0 + j < f.nrows; ++j) {
+            const short2 sp = f.spans[r0 + j];
+            const long long rowoff =
+                (long long)remap(y + f.dy_min + r0 + j, f.h, f.boundary) * f.stride;
+            for (int dx = sp.x + lane + 128; dx <= sp.y; dx += 64) {
+              const int gx = remap(x + dx, f.w, f.boundary);
+              const uint32_t vv =
+                  KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
+                               : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
+              const int pos = rb[j] + dx - sp.x;
+              if (pass == 0 && pos < kStage) stage[pos] = (uint16_t)vv;
+              if (pass == 1 && (vv >> 8) != prefix) continue;
+              atomicAdd(&hist[(vv >> sh) & 255u], 1u);
+            }
+          }
+        }
+        if (pass == 0) staged = base <= kStage;
       }
       wave_lds_sync();
       uint32_t h[4];
@@ -123,19 +177,19 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
       const uint32_t sum = h[0] + h[1] + h[2] + h[3];
       uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
       int bin = -1;
-      uint32_t base = 0;
+      uint32_t bbase = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (bin < 0 && cum <= (uint32_t)target && (uint32_t)target < cum + h[j]) {
           bin = lane * 4 + j;
-          base = cum;
+          bbase = cum;
         }
         cum += h[j];
       }
       const uint64_t who = __ballot(bin >= 0);
       const int src = __ffsll((unsigned long long)who) - 1;   // rank k always exists
       const int sbin = __builtin_amdgcn_readlane(bin, src);
-      target -= __builtin_amdgcn_readlane((int)base, src);
+      target -= __builtin_amdgcn_readlane((int)bbase, src);
       prefix = pass == 0 ? (uint32_t)sbin : ((prefix << 8) | (uint32_t)sbin);
       wave_lds_sync();
     }
@@ -340,8 +394,13 @@ using BrKernel = void (*)(mf::ImageDesc, int*);
 using FbKernel = void (*)(mf::ImageDesc, const int*, unsigned long long*);
 
 template <int KT, int SHAPE>
-void pick(const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
-  *b = mf::mf_bracket_tile_kernel<KT, SHAPE>;
+void pick(const mf::ImageDesc& br, const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
+  switch (br.imax) {
+    case 9: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 9>; break;
+    case 17: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 17>; break;
+    case 25: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 25>; break;
+    default: *b = mf::mf_bracket_tile_kernel<KT, SHAPE, 0>; break;
+  }
   if (fb.gs) {
     *f = mf::mf_fallback_gs_kernel<KT, SHAPE>;
     return;
@@ -400,11 +459,11 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
   BrKernel bk = nullptr;
   FbKernel fk = nullptr;
   if (dtype == MF_U8) {
-    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U8, mf::SHAPE_DISC>(f, &bk, &fk);
-    else pick<mf::KEY_U8, mf::SHAPE_SPANS>(f, &bk, &fk);
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U8, mf::SHAPE_DISC>(a, f, &bk, &fk);
+    else pick<mf::KEY_U8, mf::SHAPE_SPANS>(a, f, &bk, &fk);
   } else {
-    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(f, &bk, &fk);
-    else pick<mf::KEY_U16, mf::SHAPE_SPANS>(f, &bk, &fk);
+    if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(a, f, &bk, &fk);
+    else pick<mf::KEY_U16, mf::SHAPE_SPANS>(a, f, &bk, &fk);
   }
   long long fgrid = ntiles;
   if (f.gs) {
@@ -422,7 +481,7 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
                      n->tile_fail);
   hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
                      (const int*)n->tile_fail, n->fail_px);
-  const long long pgrid = std::max(1, lp.di.cus) * 4LL;
+  const long long pgrid = std::max(1, lp.di.cus) * 8LL;   // 32 waves per CU
   if (dtype == MF_U8)
     hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,
                        s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,

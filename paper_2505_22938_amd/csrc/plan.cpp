@@ -149,7 +149,10 @@ int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   d->lds_bytes = d->off_tab + tb;
   d->kt = dtype;
   d->gs = 0;
-  d->imax = 0;
+  // register-held box load for boxes of up to 25 pixels per thread, else
+  // the box streams through LDS (imax 0)
+  const int need_items = ((T + kThreads - 1) / kThreads) | 1;
+  d->imax = need_items <= 9 ? 9 : need_items <= 17 ? 17 : need_items <= 25 ? 25 : 0;
   d->slot_bytes = 0;
   d->off_x1 = d->off_lr = d->ipt = 0;
   d->br_cap = cap;

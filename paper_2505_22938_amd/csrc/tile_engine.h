@@ -51,6 +51,7 @@ enum {
   CNT_GROUPS = 6,      // lane-parallel 8-ordinal groups tested (summed over lanes)
   CNT_SORTED = 7,      // box pixels ranked by the ordinal transform (summed over tiles)
   CNT_CYC_SEED = 8,    // shader clocks per wave spent in seed solves (part of CNT_CYC_ROW)
+  CNT_CYC_LOAD = 9,    // shader clocks per wave from tile start to box loaded (part of CNT_CYC_SORT)
   CNT_SLOTS = 10
 };
 
@@ -475,6 +476,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
   const int lane = t & 63, wid = t >> 6;
   const int tx0 = (tile % a.tiles_x) * a.tw, ty0 = (tile / a.tiles_x) * a.th;
   const long long clk0 = a.counters ? (long long)clock64() : 0;
+  long long clk_load = clk0;
   const int gx0 = tx0 + a.dx_min, gy0 = ty0 + a.dy_min;
   uint32_t blo = 0, bhi = 0xffffffffu;   // bracket (keys)
   if (BR) {
@@ -514,27 +516,20 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
     const int cap = a.br_cap;
     const int nch = (T + kThreads - 1) / kThreads;   // <= 64
     const uint64_t lt = (1ull << lane) - 1ull;
-    // box coordinates of pixel c * kThreads + t, stepped per chunk
-    int lx = t % a.bw, ly = t / a.bw;
     const int sx = kThreads % a.bw, sy = kThreads / a.bw;
-    constexpr int kBatch = 8;   // chunks whose loads are in flight together
-    for (int c0 = 0; c0 < nch; c0 += kBatch) {
-      uint32_t kv[kBatch], loc[kBatch];
-      bool valid[kBatch];
+    if constexpr (IMAX > 0) {
+      // boxes of at most IMAX * kThreads pixels: every pixel's value in a
+      // register (loads all in flight), one LDS atomic per wave
+      uint32_t kv[IMAX];
+      int lx = t % a.bw, ly = t / a.bw;
+      const int sx = kThreads % a.bw, sy = kThreads / a.bw;
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const int e = (c0 + j) * kThreads + t;
-        valid[j] = c0 + j < nch && e < T;
-        loc[j] = (uint32_t)((ly << 8) | lx);
-        {
-          // unconditional: remap keeps every coordinate inside the image,
-          // so all kBatch loads are issued before the first use
-          const int gx = remap(gx0 + lx, a.w, a.boundary);
-          const int gy = remap(gy0 + ly, a.h, a.boundary);
-          const long long off = (long long)gy * a.stride + gx;
-          kv[j] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(a.img)[off]
-                               : (uint32_t)static_cast<const uint16_t*>(a.img)[off];
-        }
+      for (int i = 0; i < IMAX; ++i) {
+        const int gx = remap(gx0 + lx, a.w, a.boundary);
+        const int gy = remap(gy0 + ly, a.h, a.boundary);
+        const long long off = (long long)gy * a.stride + gx;
+        kv[i] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(a.img)[off]
+                             : (uint32_t)static_cast<const uint16_t*>(a.img)[off];
         lx += sx;
         ly += sy;
         if (lx >= a.bw) {
@@ -542,30 +537,103 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
           ly += 1;
         }
       }
-      uint64_t bal[kBatch];
       uint32_t total = 0;
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const bool below = valid[j] && kv[j] < blo, above = valid[j] && kv[j] > bhi;
-        if (c0 + j < 64) {
-          below_bits |= (uint64_t)below << (c0 + j);
-          above_bits |= (uint64_t)above << (c0 + j);
-        }
-        bal[j] = wave_ballot(valid[j] && !below && !above);
-        total += (uint32_t)__popcll(bal[j]);
+      for (int i = 0; i < IMAX; ++i) {
+        const bool valid = i * kThreads + t < T;
+        const bool below = valid && kv[i] < blo, above = valid && kv[i] > bhi;
+        below_bits |= (uint64_t)below << i;
+        above_bits |= (uint64_t)above << i;
+        total += (uint32_t)__popcll(__ballot(valid && !below && !above));
       }
       uint32_t base = 0;
       if (lane == 0 && total != 0) base = atomicAdd(ncand, total);
       base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      lx = t % a.bw;
+      ly = t / a.bw;
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const uint32_t o = base + (uint32_t)__popcll(bal[j] & lt);
-        if (((bal[j] >> lane) & 1ull) && o < (uint32_t)cap)
-          kbuf[o] = ((kv[j] - blo) << 16) | loc[j];
-        base += (uint32_t)__popcll(bal[j]);
+      for (int i = 0; i < IMAX; ++i) {
+        const bool cand = i * kThreads + t < T && !((below_bits >> i) & 1ull) &&
+                          !((above_bits >> i) & 1ull);
+        const uint64_t bal = __ballot(cand);
+        const uint32_t o = base + (uint32_t)__popcll(bal & lt);
+        if (cand && o < (uint32_t)cap)
+          kbuf[o] = ((kv[i] - blo) << 16) | (uint32_t)((ly << 8) | lx);
+        base += (uint32_t)__popcll(bal);
+        lx += sx;
+        ly += sy;
+        if (lx >= a.bw) {
+          lx -= a.bw;
+          ly += 1;
+        }
+      }
+    } else {
+    // 1a. box values into region B (free until the sort; it later holds the
+      // ordinal image): independent coalesced loads, many in flight
+      uint16_t* vals = I;
+      {
+        int lx = t % a.bw, ly = t / a.bw;
+  #pragma unroll 8
+        for (int c = 0; c < nch; ++c) {
+          const int e = c * kThreads + t;
+          const int gx = remap(gx0 + lx, a.w, a.boundary);
+          const int gy = remap(gy0 + ly, a.h, a.boundary);
+          const long long off = (long long)gy * a.stride + gx;
+          const uint16_t v = KT == KEY_U8 ? (uint16_t)static_cast<const uint8_t*>(a.img)[off]
+                                          : static_cast<const uint16_t*>(a.img)[off];
+          if (e < T) vals[e] = v;
+          lx += sx;
+          ly += sy;
+          if (lx >= a.bw) {
+            lx -= a.bw;
+            ly += 1;
+          }
+        }
+      }
+      __syncthreads();
+      // 1b. classify from LDS; append in-bracket pixels to the exchange buffer
+      {
+        int lx = t % a.bw, ly = t / a.bw;
+        constexpr int kBatch = 8;   // chunks per LDS atomic
+        for (int c0 = 0; c0 < nch; c0 += kBatch) {
+          uint32_t kv[kBatch], loc[kBatch];
+          uint64_t bal[kBatch];
+          uint32_t total = 0;
+  #pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const int e = (c0 + j) * kThreads + t;
+            const bool valid = c0 + j < nch && e < T;
+            kv[j] = valid ? (uint32_t)vals[e] : 0u;
+            loc[j] = (uint32_t)((ly << 8) | lx);
+            const bool below = valid && kv[j] < blo, above = valid && kv[j] > bhi;
+            if (c0 + j < 64) {
+              below_bits |= (uint64_t)below << (c0 + j);
+              above_bits |= (uint64_t)above << (c0 + j);
+            }
+            bal[j] = __ballot(valid && !below && !above);
+            total += (uint32_t)__popcll(bal[j]);
+            lx += sx;
+            ly += sy;
+            if (lx >= a.bw) {
+              lx -= a.bw;
+              ly += 1;
+            }
+          }
+          uint32_t base = 0;
+          if (lane == 0 && total != 0) base = atomicAdd(ncand, total);
+          base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+  #pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const uint32_t o = base + (uint32_t)__popcll(bal[j] & lt);
+            if (((bal[j] >> lane) & 1ull) && o < (uint32_t)cap)
+              kbuf[o] = ((kv[j] - blo) << 16) | loc[j];
+            base += (uint32_t)__popcll(bal[j]);
+          }
+        }
       }
     }
     __syncthreads();
+    clk_load = a.counters ? (long long)clock64() : 0;
     const int Ts = (int)*ncand;
     if (Ts > cap) return true;   // more in-bracket pixels than region A holds
     // 2. ordinal transform of the candidates, ordinals 1..Ts; passes cover
@@ -614,6 +682,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
         }
       }
     }
+    clk_load = a.counters ? (long long)clock64() : 0;
     // 2. ordinal transform
     const int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
     if (KT == KEY_F32)
@@ -829,6 +898,7 @@ __device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned
     atomicAdd(&a.counters[CNT_CYC_SWEEP], (unsigned long long)(clk3 - clk2));
     atomicAdd(&a.counters[CNT_WAVES], 1ull);
     atomicAdd(&a.counters[CNT_CYC_SEED], (unsigned long long)seed_clk);
+    atomicAdd(&a.counters[CNT_CYC_LOAD], (unsigned long long)(clk_load - clk0));
   }
   if (a.counters) {
     // lane-parallel groups differ per lane: sum over the wave

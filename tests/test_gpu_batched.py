@@ -104,3 +104,33 @@ def test_batched_rejects_aliasing(mf):
     fp = mf.Footprint.disc(2)
     with pytest.raises(mf.MedianFilterError):
         mf.BatchPlan([(a, b, fp, "clamp"), (b, a, fp, "clamp")])
+
+
+def test_batched_full_mixed_batch_sampled(mf, oracle_mod):
+    """The full 64-image mixed batch (w, h in 128..2048, u8/u16/f32, disc
+    radius 1..64, clamp) in one captured launch: every pixel equals the
+    plain filter's and 48 seeded pixels per image equal the oracle's."""
+    batch = workloads.mixed_batch(64, 3)
+    fps, items, plain = {}, [], []
+    for img_np, s in batch:
+        r = s["radius"]
+        if r not in fps:
+            fps[r] = mf.Footprint.disc(r)
+        d = dev(img_np)
+        items.append((d, torch.empty_like(d), fps[r], "clamp"))
+        plain.append(mf.median_filter(d, fps[r], "clamp"))
+    plan = mf.BatchPlan(items)
+    s = torch.cuda.Stream()
+    plan.capture(s)
+    plan.replay(s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    for i, ((img_np, sp), it, p) in enumerate(zip(batch, items, plain)):
+        got = it[1].cpu().numpy()
+        assert np.array_equal(got.view(np.uint8), p.cpu().numpy().view(np.uint8)), i
+        rng = np.random.default_rng(i)
+        h, w = img_np.shape
+        xs, ys = rng.integers(0, w, 48), rng.integers(0, h, 48)
+        exp = oracle_mod.filter_points(img_np, OF.disc(sp["radius"]), xs, ys, "clamp")
+        assert np.array_equal(got[ys, xs].view(np.uint8), exp.view(np.uint8)), (i, sp)
+    plan.close()

@@ -304,3 +304,29 @@ def test_trained_network_gain_over_plain(mf, oracle_mod):
         assert fb <= 0.1 * 512 * 384, (r, fb)
     assert max(ranked.values()) < 0.5, ranked
     net.close()
+
+
+@pytest.mark.parametrize("kind", ["uniform", "natural"])
+def test_learned_full_size_sampled(mf, oracle_mod, kind):
+    """2048x2048 uint16 (the learned-proposal workload) at radii 16, 32, 64
+    with the committed network: every pixel equals the plain filter's and
+    2000 seeded pixels equal the oracle's."""
+    import os
+    net = mf.LearnedNet.load(os.path.join(os.path.dirname(mf.__file__), "weights",
+                                          "bracket_net.npz"))
+    img_np = (workloads.uniform_u16(2048, 2048, seed=4) if kind == "uniform"
+              else workloads.natural_u16(2048, 2048, seed=4))
+    img = dev(img_np)
+    for r in (16, 32, 64):
+        fp = mf.Footprint.disc(r)
+        out, fb = net.filter(img, fp)
+        ref = mf.median_filter(img, fp, "clamp")
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got, ref.cpu().numpy()), r
+        rng = np.random.default_rng(r)
+        xs, ys = rng.integers(0, 2048, 2000), rng.integers(0, 2048, 2000)
+        exp = oracle_mod.filter_points(img_np, OF.disc(r), xs, ys, "clamp")
+        assert np.array_equal(got[ys, xs], exp), r
+        assert 0 <= fb <= 2048 * 2048
+    net.close()

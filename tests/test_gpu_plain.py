@@ -206,3 +206,21 @@ def test_plain_large_radius_odd_tiles(mf, oracle_mod, tile):
                     oracle_mod.filter(img, OF.disc(100), "clamp"), f"r100 {tile}")
     finally:
         mf.set_tile_override(0, 0)
+
+
+@pytest.mark.parametrize("name", ["disc48", "ellipse", "hexagon"])
+def test_lognormal_f32_full_size_sampled(mf, oracle_mod, name):
+    """3840x2160 float32 log-normal plane with +-1e6 outliers, mirror
+    boundary, at full size in the default launch configuration; 3000
+    seeded output pixels against the oracle."""
+    mk = {"disc48": (lambda: mf.Footprint.disc(48), lambda: OF.disc(48)),
+          "ellipse": (lambda: mf.Footprint.ellipse(60, 20, 30), lambda: OF.ellipse(60, 20, 30)),
+          "hexagon": (lambda: mf.Footprint.regular_polygon(6, 40), lambda: OF.regular_polygon(6, 40))}
+    a, b = mk[name]
+    img = workloads.lognormal_f32(3840, 2160, planes=1, seed=2)[0]
+    got = run(mf, img, a(), "mirror")
+    rng = np.random.default_rng(7)
+    xs = rng.integers(0, 3840, 3000)
+    ys = rng.integers(0, 2160, 3000)
+    exp = oracle_mod.filter_points(img, b(), xs, ys, "mirror")
+    assert np.array_equal(got[ys, xs].view(np.uint32), exp.view(np.uint32))
