@@ -367,10 +367,25 @@ def main():
         v1 = oracle.filter_points(img_np, ofp, xs1, ys1, "clamp", nthreads=cores)
         d1 = time.perf_counter() - c1
         mismatches = int((gpu_out[ys, xs] != v0).sum() + (gpu_out[ys1, xs1] != v1).sum())
+        # one thread on a 128x128 crop of output pixels, for scaling
+        cy, cx = np.mgrid[0:128, 0:128]
+        c2 = time.perf_counter()
+        v2 = oracle.filter_points(img_np, ofp, cx.ravel() + S // 2, cy.ravel() + S // 2, "clamp",
+                                  nthreads=1)
+        d2 = time.perf_counter() - c2
+        mismatches += int((gpu_out[cy.ravel() + S // 2, cx.ravel() + S // 2] != v2).sum())
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                             "")
+        except OSError:
+            pass
         cpu = {"value": n1 / d1 / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+               "cpu_model": model, "one_thread_mpx_s": 128 * 128 / d2 / 1e6,
                "sample": f"{n1} random output pixels of the same {S}x{S} image, disc r={r} "
                          f"({fp.taps} taps), brute force gather + nth_element, {d1:.1f}s",
-               "mismatches_vs_gpu": mismatches, "checked_px": n0 + n1}
+               "mismatches_vs_gpu": mismatches, "checked_px": n0 + n1 + 128 * 128}
 
     line = {
         "metric": "Mpixel/s, r=32 disc uint16 4K, learned/batched vs plain GPU, bit-exact",
