@@ -129,19 +129,28 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
  *
  * mf_plan_create validates every entry (as median_filter does, plus no
  * output may overlap any input or other output: MF_ERR_ALIAS), plans each
- * image (the tuned tile shape for its dtype and footprint when the tuned
- * table has one -- loaded first from `tune_cache_path` if not NULL -- else
- * the default choice), and allocates the device tables: a descriptor per
- * image, one queue of all tiles ordered longest-estimated-first, two queue
- * counters and, if some image needs it, global scratch.  The plan keeps the
- * buffer pointers of `descs` (the device images themselves are not copied):
- * they must stay valid for every launch.  The footprints must outlive the
- * plan.  Synchronous.
+ * image exactly as median_filter would (the tuned tile shape for its dtype
+ * and footprint when the tuned table has one -- loaded first from
+ * `tune_cache_path` if not NULL -- else the default choice), groups all
+ * tiles by kernel variant (dtype, footprint form, register capacity or
+ * global scratch), orders each group longest-estimated-first, and allocates
+ * the device tables: a descriptor per image, the tile queue, two counters
+ * per group and, if some image needs it, global scratch; it also creates up
+ * to three streams and four events of its own (default priority).  The plan
+ * keeps the buffer pointers of `descs` (the device images themselves are
+ * not copied): they must stay valid for every launch.  The footprints must
+ * outlive the plan.  Synchronous.
  *
- * mf_plan_launch queues one persistent kernel on `stream`: CUs x occupancy
- * workgroups pop tiles until the queue is empty; the last one resets the
- * counters, so launches need no memset, allocate nothing, and may be
- * captured in a graph.  Launches of one plan must not overlap in time.
+ * mf_plan_launch queues one kernel per group: global-scratch groups run a
+ * persistent grid (CUs x occupancy workgroups popping tiles; the last one
+ * resets the group's counters), the others one workgroup per tile.  With
+ * more than one group it records an event on `stream`, makes the plan's
+ * streams wait for it, spreads the groups over `stream` and those streams
+ * (largest estimated total first, each onto the least loaded), and makes
+ * `stream` wait for all of them again, so the whole launch is ordered on
+ * `stream` like a single kernel.  Launches need no memset, allocate
+ * nothing, and may be captured in a graph.  Launches of one plan must not
+ * overlap in time.
  *
  * mf_plan_capture captures mf_plan_launch on `stream` (not the null
  * stream) into a hipGraph owned by the plan; mf_plan_replay launches that
@@ -166,9 +175,13 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
 int mf_plan_launch(mf_plan* plan, hipStream_t stream);
 int mf_plan_capture(mf_plan* plan, hipStream_t stream);
 int mf_plan_replay(mf_plan* plan, hipStream_t stream);
-/* Total tiles, workgroups per launch, LDS bytes per workgroup, scratch bytes. */
+/* Total tiles, workgroups per launch (summed over groups), the largest LDS
+ * bytes per workgroup, scratch bytes.  Any output pointer may be NULL. */
 int mf_plan_info(const mf_plan* plan, int* tiles, int* grid, int* lds_bytes,
                  long long* scratch_bytes);
+/* Number of kernel groups a launch runs and of streams it spreads them over
+ * (0 and 0 for an empty plan).  Any output pointer may be NULL. */
+int mf_plan_groups(const mf_plan* plan, int* groups, int* streams);
 void mf_plan_destroy(mf_plan* plan);
 int median_filter_batched(const mf_image_desc* descs, int n, hipStream_t stream);
 

@@ -65,6 +65,7 @@ def lib():
         "mf_plan_capture": ([P, P], I),
         "mf_plan_replay": ([P, P], I),
         "mf_plan_info": ([P, IP, IP, IP, ctypes.POINTER(ctypes.c_longlong)], I),
+        "mf_plan_groups": ([P, IP, IP], I),
         "mf_plan_destroy": ([P], None),
         "median_filter_batched": ([P, I, P], I),
         "mf_mfma_probe": ([P, P, P, P], I),
@@ -325,7 +326,10 @@ class BatchPlan:
         s = ctypes.c_longlong()
         _check("mf_plan_info", lib().mf_plan_info(self._h, ctypes.byref(t), ctypes.byref(g),
                                                   ctypes.byref(l), ctypes.byref(s)))
-        return dict(tiles=t.value, grid=g.value, lds_bytes=l.value, scratch_bytes=s.value)
+        ng, ns = ctypes.c_int(), ctypes.c_int()
+        _check("mf_plan_groups", lib().mf_plan_groups(self._h, ctypes.byref(ng), ctypes.byref(ns)))
+        return dict(tiles=t.value, grid=g.value, lds_bytes=l.value, scratch_bytes=s.value,
+                    groups=ng.value, streams=ns.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -1,14 +1,20 @@
-// Batched filtering: many images (any sizes, dtypes, footprints) in one
-// persistent launch, optionally captured in a hipGraph.  Not in the paper;
-// the per-tile work is the same engine as the plain filter.
+// Batched filtering: many images (any sizes, dtypes, footprints) in a few
+// launches, optionally captured in a hipGraph.  Not in the paper; the
+// per-tile work is the same engine as the plain filter.
 //
 // mf_plan_create builds, per image, the plain filter's plan (tuned shape if
-// one is recorded), a device descriptor table, and one queue of all tiles of
-// all images, ordered longest-estimated-first.  The kernel runs one
-// workgroup per resident slot (CUs x occupancy); each workgroup pops tiles
-// from the queue with an atomic counter and runs them.  The last workgroup
-// to find the queue empty resets the counters, so a launch needs no memset
-// and can be replayed from a graph.
+// one is recorded) and a device descriptor table, then splits all tiles of
+// all images into groups that share a kernel instance (key type, footprint
+// form, register capacity or global scratch), so that each instance keeps
+// the register allocation of the plain kernel for that variant.  A group is
+// a slice of one tile queue, ordered longest-estimated-first, run by one
+// launch: one workgroup per tile in queue order for LDS tiles, a persistent
+// grid popping tiles with an atomic counter for global-scratch tiles.  The
+// groups are spread over up to four streams (the caller's and three the plan
+// owns, forked from and joined back into the caller's with events), longest
+// total first, so that one group's tail overlaps the next group's start.
+// Persistent launches reset their own counters when done, so launches need
+// no memset and can be replayed from a graph.
 
 #include <hip/hip_runtime.h>
 
@@ -21,44 +27,54 @@
 
 namespace mf {
 
-constexpr int kBatchItems = 25;   // register capacity of LDS plans in a batch
+constexpr int kMaxItems = 33;  // register capacity allowed to batch plans (as plain)
+constexpr int kLanes = 4;      // streams a launch spreads its groups over
 
-template <int KT, int SHAPE>
-__device__ __forceinline__ void run_tile(const ImageDesc& d, int tile, unsigned char* smem,
-                                         unsigned char* slot) {
-  if (d.gs) tile_body<KT, SHAPE, 1, true>(d, tile, smem, slot);
-  else tile_body<KT, SHAPE, kBatchItems, false>(d, tile, smem, nullptr);
-}
+// Descriptors are read through the constant address space, so the tile body
+// loads each field with a scalar load where it is used, as it does a kernel
+// argument, instead of holding a copy in registers.
+using ConstDesc = const __attribute__((address_space(4))) ImageDesc;
 
-__global__ __launch_bounds__(kThreads) void mf_batched_kernel(const ImageDesc* __restrict__ descs,
+// Register-capacity (LDS) groups: one workgroup per tile of the slice, in
+// queue order, so the longest tiles are dispatched first.
+template <int KT, int SHAPE, int IMAX>
+__global__ __launch_bounds__(kThreads) void mf_batched_kernel(ConstDesc* descs,
                                                               const int2* __restrict__ queue,
-                                                              int ntotal, int* counters,
+                                                              int begin, int end, int* counters,
                                                               unsigned char* scratch,
                                                               long long slot_bytes) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int s_item;
-  unsigned char* slot = scratch ? scratch + (long long)blockIdx.x * slot_bytes : nullptr;
+  const int2 q = queue[begin + blockIdx.x];
+  const int img = __builtin_amdgcn_readfirstlane(q.x);
+  const int tile = __builtin_amdgcn_readfirstlane(q.y);
+  tile_body<KT, SHAPE, IMAX, false>(descs[img], tile, smem, nullptr);
+}
+
+// Global-scratch groups: a persistent grid, one scratch slot per workgroup;
+// workgroups pop tiles with an atomic counter.  The last workgroup to find
+// the slice empty resets its counters for the next launch.
+template <int KT, int SHAPE>
+__global__ __launch_bounds__(kThreads) void mf_batched_gs_kernel(ConstDesc* descs,
+                                                                 const int2* __restrict__ queue,
+                                                                 int begin, int end,
+                                                                 int* counters,
+                                                                 unsigned char* scratch,
+                                                                 long long slot_bytes) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int* s_item = reinterpret_cast<int*>(smem);  // free between tiles
+  unsigned char* slot = scratch + (long long)blockIdx.x * slot_bytes;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1);
+    if (threadIdx.x == 0) *s_item = begin + atomicAdd(&counters[0], 1);
     __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    const int item = __builtin_amdgcn_readfirstlane(*s_item);
     __syncthreads();
-    if (item >= ntotal) break;
+    if (item >= end) break;
     const int2 q = queue[item];
     const int img = __builtin_amdgcn_readfirstlane(q.x);
     const int tile = __builtin_amdgcn_readfirstlane(q.y);
-    const ImageDesc d = descs[img];
-    switch (d.kt * 2 + d.shape) {
-      case KEY_U8 * 2 + SHAPE_DISC: run_tile<KEY_U8, SHAPE_DISC>(d, tile, smem, slot); break;
-      case KEY_U8 * 2 + SHAPE_SPANS: run_tile<KEY_U8, SHAPE_SPANS>(d, tile, smem, slot); break;
-      case KEY_U16 * 2 + SHAPE_DISC: run_tile<KEY_U16, SHAPE_DISC>(d, tile, smem, slot); break;
-      case KEY_U16 * 2 + SHAPE_SPANS: run_tile<KEY_U16, SHAPE_SPANS>(d, tile, smem, slot); break;
-      case KEY_F32 * 2 + SHAPE_DISC: run_tile<KEY_F32, SHAPE_DISC>(d, tile, smem, slot); break;
-      default: run_tile<KEY_F32, SHAPE_SPANS>(d, tile, smem, slot); break;
-    }
+    tile_body<KT, SHAPE, 1, true>(descs[img], tile, smem, slot);
     __syncthreads();
   }
-  // the last workgroup out resets the queue for the next launch
   if (threadIdx.x == 0) {
     __threadfence();
     if (atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
@@ -69,6 +85,36 @@ __global__ __launch_bounds__(kThreads) void mf_batched_kernel(const ImageDesc* _
 }
 
 namespace {
+
+using BatchFn = void (*)(ConstDesc*, const int2*, int, int, int*, unsigned char*,
+                         long long);
+
+// Kernel variant of a planned image: 0..3 = register capacity 9/17/25/33,
+// 4 = global scratch.
+int variant_of(const ImageDesc& d) {
+  if (d.gs) return 4;
+  return d.imax <= 9 ? 0 : d.imax <= 17 ? 1 : d.imax <= 25 ? 2 : 3;
+}
+
+template <int KT, int SHAPE>
+BatchFn pick_batched_variant(int v) {
+  switch (v) {
+    case 0: return mf_batched_kernel<KT, SHAPE, 9>;
+    case 1: return mf_batched_kernel<KT, SHAPE, 17>;
+    case 2: return mf_batched_kernel<KT, SHAPE, 25>;
+    case 3: return mf_batched_kernel<KT, SHAPE, 33>;
+    default: return mf_batched_gs_kernel<KT, SHAPE>;
+  }
+}
+
+BatchFn pick_batched(int kt, int shape, int v) {
+  if (kt == MF_U8) return shape == SHAPE_DISC ? pick_batched_variant<KEY_U8, SHAPE_DISC>(v)
+                                              : pick_batched_variant<KEY_U8, SHAPE_SPANS>(v);
+  if (kt == MF_U16) return shape == SHAPE_DISC ? pick_batched_variant<KEY_U16, SHAPE_DISC>(v)
+                                               : pick_batched_variant<KEY_U16, SHAPE_SPANS>(v);
+  return shape == SHAPE_DISC ? pick_batched_variant<KEY_F32, SHAPE_DISC>(v)
+                             : pick_batched_variant<KEY_F32, SHAPE_SPANS>(v);
+}
 
 // Relative tile cost for longest-first ordering: sort work over the box plus
 // slide and scan work over the tile's pixels.
@@ -85,19 +131,35 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 }  // namespace
 
+// One persistent launch of a batch plan: a slice of the queue run by one
+// kernel instance.
+struct BatchGroup {
+  BatchFn fn = nullptr;
+  int begin = 0, end = 0;   // queue slice
+  int grid = 0;
+  int lds_bytes = 0;
+  long long slot_bytes = 0;
+  long long scratch_off = 0;
+  int lane = 0;             // 0 = caller's stream, 1.. = the plan's streams
+  double cost = 0;
+};
+
 }  // namespace mf
 
 struct mf_plan {
   int dev = 0;
   int n = 0;
   int ntotal = 0;
-  int grid = 0;
-  int lds_bytes = 0;
-  long long slot_bytes = 0;
+  int nlanes = 1;
+  std::vector<mf::BatchGroup> groups;
   mf::ImageDesc* d_descs = nullptr;
   int2* d_queue = nullptr;
   int* d_counters = nullptr;
   unsigned char* d_scratch = nullptr;
+  long long scratch_bytes = 0;
+  hipStream_t side[mf::kLanes - 1] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[mf::kLanes - 1] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -112,6 +174,11 @@ void mf_plan_destroy(mf_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (int i = 0; i < mf::kLanes - 1; ++i) {
+    if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+    if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
   (void)hipFree(p->d_descs);
   (void)hipFree(p->d_queue);
   (void)hipFree(p->d_counters);
@@ -152,7 +219,14 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
   p->dev = dev;
   p->n = n;
   std::vector<ImageDesc> hd(n);
-  std::vector<std::pair<double, int2>> items;
+  // (group key, -cost, image, tile): sorted, each group's tiles are one
+  // contiguous slice, longest first
+  struct Item {
+    int key;
+    double cost;
+    int2 it;
+  };
+  std::vector<Item> items;
   for (int i = 0; i < n; ++i) {
     const mf_image_desc& e = descs[i];
     if (!e.w || !e.h) {
@@ -161,31 +235,65 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
     }
     const void* table = nullptr;
     if ((rc = footprint_device_table(e.fp, dev, &table)) ||
-        (rc = choose_plan(e.dtype, e.fp, di.lds_max - 256, kBatchItems, &hd[i]))) {
+        (rc = choose_plan(e.dtype, e.fp, di.lds_max, kMaxItems, &hd[i]))) {
       mf_plan_destroy(p);
       return rc;
     }
     bind_image(&hd[i], e.img, e.w, e.h, e.stride_bytes, e.dtype, e.fp, e.boundary,
                (e.fp->taps - 1) / 2, table);
     hd[i].out = e.out;
-    p->lds_bytes = std::max(p->lds_bytes, hd[i].lds_bytes);
-    if (hd[i].gs) p->slot_bytes = std::max(p->slot_bytes, hd[i].slot_bytes);
+    const int key = (hd[i].kt * 2 + hd[i].shape) * 5 + variant_of(hd[i]);
     const double c = tile_cost(hd[i]);
     const int nt = hd[i].tiles_x * hd[i].tiles_y;
-    for (int t = 0; t < nt; ++t) items.push_back({c, make_int2(i, t)});
+    for (int t = 0; t < nt; ++t) items.push_back({key, c, make_int2(i, t)});
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.key != b.key ? a.key < b.key : a.cost > b.cost;
+  });
   p->ntotal = (int)items.size();
-  const int occ = std::max(1, std::min(2, di.lds_max / std::max(1, p->lds_bytes)));
-  p->grid = std::max(1, std::min(p->ntotal, di.cus * occ));
   std::vector<int2> q(items.size());
-  for (size_t i = 0; i < items.size(); ++i) q[i] = items[i].second;
+  for (size_t i = 0; i < items.size(); ++i) q[i] = items[i].it;
+  // one group per key, sized like the plain filter's launch of that variant
+  for (size_t i = 0; i < items.size();) {
+    size_t j = i;
+    BatchGroup g;
+    const ImageDesc& d0 = hd[items[i].it.x];
+    g.fn = pick_batched(d0.kt, d0.shape, variant_of(d0));
+    for (; j < items.size() && items[j].key == items[i].key; ++j) {
+      const ImageDesc& d = hd[items[j].it.x];
+      g.lds_bytes = std::max(g.lds_bytes, d.lds_bytes);
+      if (d.gs) g.slot_bytes = std::max(g.slot_bytes, d.slot_bytes);
+      g.cost += items[j].cost;
+    }
+    g.begin = (int)i;
+    g.end = (int)j;
+    const int occ = std::max(1, std::min(2, di.lds_max / std::max(1, g.lds_bytes)));
+    g.grid = g.slot_bytes ? std::max(1, std::min(g.end - g.begin, di.cus * occ))
+                          : g.end - g.begin;
+    g.scratch_off = p->scratch_bytes;
+    p->scratch_bytes += (long long)g.grid * g.slot_bytes;
+    p->groups.push_back(g);
+    i = j;
+  }
+  // longest group first, each onto the least loaded stream
+  std::stable_sort(p->groups.begin(), p->groups.end(),
+                   [](const BatchGroup& a, const BatchGroup& b) { return a.cost > b.cost; });
+  p->nlanes = std::max(1, std::min<int>(kLanes, (int)p->groups.size()));
+  {
+    double load[kLanes] = {};
+    for (BatchGroup& g : p->groups) {
+      int best = 0;
+      for (int l = 1; l < p->nlanes; ++l)
+        if (load[l] < load[best]) best = l;
+      g.lane = best;
+      load[best] += g.cost;
+    }
+  }
+  const size_t ng = std::max<size_t>(1, p->groups.size());
   if (hipMalloc(&p->d_descs, sizeof(ImageDesc) * std::max(1, n)) != hipSuccess ||
       hipMalloc(&p->d_queue, sizeof(int2) * std::max<size_t>(1, q.size())) != hipSuccess ||
-      hipMalloc(&p->d_counters, 2 * sizeof(int)) != hipSuccess ||
-      (p->slot_bytes &&
-       hipMalloc(&p->d_scratch, (size_t)p->grid * (size_t)p->slot_bytes) != hipSuccess)) {
+      hipMalloc(&p->d_counters, 2 * sizeof(int) * ng) != hipSuccess ||
+      (p->scratch_bytes && hipMalloc(&p->d_scratch, (size_t)p->scratch_bytes) != hipSuccess)) {
     mf_plan_destroy(p);
     return MF_ERR_NOMEM;
   }
@@ -194,12 +302,26 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
       (!q.empty() &&
        hipMemcpy(p->d_queue, q.data(), sizeof(int2) * q.size(), hipMemcpyHostToDevice) !=
            hipSuccess) ||
-      hipMemset(p->d_counters, 0, 2 * sizeof(int)) != hipSuccess) {
+      hipMemset(p->d_counters, 0, 2 * sizeof(int) * ng) != hipSuccess) {
     mf_plan_destroy(p);
     return MF_ERR_HIP;
   }
-  (void)hipFuncSetAttribute((const void*)mf_batched_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, p->lds_bytes);
+  if (p->nlanes > 1) {
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess) {
+      p->fork = nullptr;
+      mf_plan_destroy(p);
+      return MF_ERR_HIP;
+    }
+    for (int l = 0; l < p->nlanes - 1; ++l)
+      if (hipStreamCreateWithFlags(&p->side[l], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&p->join[l], hipEventDisableTiming) != hipSuccess) {
+        mf_plan_destroy(p);
+        return MF_ERR_HIP;
+      }
+  }
+  for (const BatchGroup& g : p->groups)
+    (void)hipFuncSetAttribute((const void*)g.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              g.lds_bytes);
   *out = p;
   return MF_OK;
 }
@@ -207,10 +329,27 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
 int mf_plan_launch(mf_plan* p, hipStream_t stream) {
   if (!p) return MF_ERR_INVALID_ARG;
   if (p->ntotal == 0) return MF_OK;
-  hipLaunchKernelGGL(mf::mf_batched_kernel, dim3(p->grid), dim3(mf::kThreads), p->lds_bytes,
-                     stream, p->d_descs, p->d_queue, p->ntotal, p->d_counters, p->d_scratch,
-                     p->slot_bytes);
-  return hipGetLastError() == hipSuccess ? MF_OK : MF_ERR_HIP;
+  const bool fork = p->nlanes > 1;
+  if (fork) {
+    if (hipEventRecord(p->fork, stream) != hipSuccess) return MF_ERR_HIP;
+    for (int l = 0; l < p->nlanes - 1; ++l)
+      if (hipStreamWaitEvent(p->side[l], p->fork, 0) != hipSuccess) return MF_ERR_HIP;
+  }
+  int rc = MF_OK;
+  for (size_t i = 0; i < p->groups.size(); ++i) {
+    const mf::BatchGroup& g = p->groups[i];
+    hipStream_t s = g.lane ? p->side[g.lane - 1] : stream;
+    hipLaunchKernelGGL(g.fn, dim3(g.grid), dim3(mf::kThreads), g.lds_bytes, s,
+                       (mf::ConstDesc*)p->d_descs, p->d_queue, g.begin, g.end, p->d_counters + 2 * i,
+                       g.slot_bytes ? p->d_scratch + g.scratch_off : nullptr, g.slot_bytes);
+    if (hipGetLastError() != hipSuccess) rc = MF_ERR_HIP;
+  }
+  if (fork)  // join every forked stream back, also after a failed launch
+    for (int l = 0; l < p->nlanes - 1; ++l)
+      if (hipEventRecord(p->join[l], p->side[l]) != hipSuccess ||
+          hipStreamWaitEvent(stream, p->join[l], 0) != hipSuccess)
+        rc = MF_ERR_HIP;
+  return rc;
 }
 
 int mf_plan_capture(mf_plan* p, hipStream_t stream) {
@@ -247,10 +386,22 @@ int mf_plan_replay(mf_plan* p, hipStream_t stream) {
 int mf_plan_info(const mf_plan* p, int* tiles, int* grid, int* lds_bytes,
                  long long* scratch_bytes) {
   if (!p) return MF_ERR_INVALID_ARG;
+  int wg = 0, lds = 0;
+  for (const mf::BatchGroup& g : p->groups) {
+    wg += g.grid;
+    lds = std::max(lds, g.lds_bytes);
+  }
   if (tiles) *tiles = p->ntotal;
-  if (grid) *grid = p->grid;
-  if (lds_bytes) *lds_bytes = p->lds_bytes;
-  if (scratch_bytes) *scratch_bytes = (long long)p->grid * p->slot_bytes;
+  if (grid) *grid = wg;
+  if (lds_bytes) *lds_bytes = lds;
+  if (scratch_bytes) *scratch_bytes = p->scratch_bytes;
+  return MF_OK;
+}
+
+int mf_plan_groups(const mf_plan* p, int* groups, int* streams) {
+  if (!p) return MF_ERR_INVALID_ARG;
+  if (groups) *groups = (int)p->groups.size();
+  if (streams) *streams = p->groups.empty() ? 0 : p->nlanes;
   return MF_OK;
 }
 

@@ -103,8 +103,8 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
 // Membership of the eight omnigram entries in g (two per word), bit j for
 // entry j.  Disc: per entry one byte permute, one packed subtract and one
 // dot product whose sign bit is shifted into the mask (v_alignbit).
-template <int SHAPE>
-__device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, const ImageDesc& a,
+template <int SHAPE, typename D>
+__device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, const D& a,
                                                const short2* rsp) {
   const uint32_t wv[4] = {g.x, g.y, g.z, g.w};
   if constexpr (SHAPE == SHAPE_DISC) {
@@ -144,9 +144,9 @@ __device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, con
 // possible when some pixels are outside the omnigram, see BR below); c_end
 // then receives the number of members below the end reached (below T going
 // up, below ordinal 0 going down).
-template <int SHAPE>
+template <int SHAPE, typename D>
 __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int T,
-                                         const ImageDesc& a, const uint16_t* om,
+                                         const D& a, const uint16_t* om,
                                          const short2* rsp, int& blocks, uint32_t pre_up,
                                          uint32_t pre_dn, int& c_end) {
   const int lane = threadIdx.x & 63;
@@ -199,9 +199,9 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
   return -1;
 }
 
-template <int KT, int SHAPE>
+template <int KT, int SHAPE, typename D>
 __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, int T,
-                                           const ImageDesc& a, const uint16_t* om,
+                                           const D& a, const uint16_t* om,
                                            const short2* rsp, int& blocks, int& c_end) {
   const int lane = threadIdx.x & 63;
   const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
@@ -219,9 +219,9 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, 
 // entries located outside the box, so only the first group needs a range
 // test.  After `budget` groups an unfinished lane returns -1 with (p, c) set
 // to its frontier, for a wave-cooperative finish.
-template <int SHAPE>
+template <int SHAPE, typename D>
 __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget, int T,
-                                           const ImageDesc& a, const uint16_t* om,
+                                           const D& a, const uint16_t* om,
                                            const short2* rsp, int& groups) {
   const bool up = c <= k;
   int need = up ? k - c : c - 1 - k;
@@ -295,8 +295,8 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 // and 0xffff for every pixel above it.  If the median is below (above) the
 // bracket, returns -1 with esc_p = 1 (T) and esc_c = the exact number of
 // window members below that ordinal, so sliding can go on from there.
-template <int KT, int SHAPE, bool BR>
-__device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, const ImageDesc& a,
+template <int KT, int SHAPE, bool BR, typename D>
+__device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, const D& a,
                                           const uint16_t* om, const uint16_t* I, uint32_t* hist,
                                           const short2* rsp, int& blocks, int& esc_p,
                                           int& esc_c) {
@@ -365,7 +365,8 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, con
 // pixel, against pivot p: lanes take footprint rows lane and lane + 64 (and
 // further rounds of 128 rows for taller windows); hrow[i] = (entering
 // offset, leaving offset) of row i.
-__device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDesc& a,
+template <typename D>
+__device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a,
                                            const uint16_t* I, const int2* hrow,
                                            const int4& own) {
   const int lane = threadIdx.x & 63;
@@ -397,8 +398,8 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const ImageDes
 
 // Reverse map (paper, "Method Summary" step 7): the output is C[m].  For
 // bracketed tiles the stored key is relative to the bracket's low end lo.
-template <int KT>
-__device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, const uint32_t* kbuf,
+template <int KT, typename D>
+__device__ __forceinline__ void store_out(const D& a, int gx, int gy, const uint32_t* kbuf,
                                           const uint16_t* crev, int m, uint32_t lo) {
   const long long o = (long long)gy * a.stride + gx;
   if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)(crev[m] + lo);
@@ -408,7 +409,8 @@ __device__ __forceinline__ void store_out(const ImageDesc& a, int gx, int gy, co
 
 // Bracketed tiles: append the flagged output pixels of the wave (index
 // y * w + x) to the miss list.  Call with the whole wave.
-__device__ __forceinline__ void push_misses(const ImageDesc& a, bool missed, int gx, int gy) {
+template <typename D>
+__device__ __forceinline__ void push_misses(const D& a, bool missed, int gx, int gy) {
   const uint64_t mb = wave_ballot(missed);
   if (mb == 0) return;
   const int lane = threadIdx.x & 63;
@@ -453,8 +455,8 @@ __device__ __forceinline__ void br_sort(uint32_t* kbuf, int Ts, int passes, uint
 // pass) and the sweep goes on.  Returns true, with nothing written, if the
 // tile has more in-bracket pixels than region A holds (the caller then runs
 // the plain body on it); always false without BR.
-template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false>
-__device__ __forceinline__ bool tile_body(const ImageDesc& a, int tile, unsigned char* smem,
+template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false, typename D>
+__device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* smem,
                                           unsigned char* gslot) {
   static_assert(!(GS && BR), "bracketed tiles use the LDS variant");
   const int T = a.T;

@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent launch: every image of a mixed batch
+"""GPU parity of the batched launch: every image of a mixed batch
 equals the plain filter's output and the oracle's, bit for bit, and graph
 replays reproduce it."""
 
@@ -95,6 +95,62 @@ def test_batched_graph_replays(mf, oracle_mod):
     plan.launch()
     torch.cuda.synchronize()
     check(items, hosts, oracle_mod, "eager after replay")
+    plan.close()
+
+
+def test_batched_groups_on_forked_streams(mf, oracle_mod):
+    """Tiles needing different kernel variants (8-bit small window, 16-bit
+    window large enough for global scratch, float32, several register
+    capacities) run as separate groups spread over forked streams: eager
+    launches on a side stream and on the current stream, and graph replays
+    with eager work between them, all equal the oracle."""
+    cases = [("u8", 90, 64, 3), ("u16", 150, 120, 60), ("f32", 100, 70, 12),
+             ("u16", 200, 40, 20), ("u8", 33, 250, 30), ("f32", 64, 64, 40)]
+    items, hosts = [], []
+    for i, (dt, w, h, r) in enumerate(cases):
+        img = workloads.uniform(w, h, dt, 40 + i)
+        d = dev(img)
+        items.append((d, torch.empty_like(d), mf.Footprint.disc(r), "mirror"))
+        hosts.append((img, r, "mirror"))
+    plan = mf.BatchPlan(items)
+    info = plan.info()
+    assert info["groups"] >= 3 and info["streams"] >= 2, info
+    assert info["scratch_bytes"] > 0, info
+    side = torch.cuda.Stream()
+    plan.launch(side)
+    side.synchronize()
+    check(items, hosts, oracle_mod, "launch on a side stream")
+    for _, out, _, _ in items:
+        out.zero_()
+    plan.launch()
+    torch.cuda.synchronize()
+    check(items, hosts, oracle_mod, "launch on the current stream")
+    plan.capture(side)
+    for rep in range(3):
+        for _, out, _, _ in items:
+            out.zero_()
+        torch.cuda.synchronize()
+        plan.replay(side)
+        side.synchronize()
+        check(items, hosts, oracle_mod, f"replay {rep}")
+    plan.close()
+
+
+def test_batched_single_group_plan(mf, oracle_mod):
+    """A batch whose images all use one kernel variant runs as one group on
+    the caller's stream."""
+    items, hosts = [], []
+    for i, (w, h) in enumerate([(70, 50), (130, 90), (64, 64)]):
+        img = workloads.uniform(w, h, "u8", 60 + i)
+        d = dev(img)
+        items.append((d, torch.empty_like(d), mf.Footprint.disc(2), "clamp"))
+        hosts.append((img, 2, "clamp"))
+    plan = mf.BatchPlan(items)
+    info = plan.info()
+    assert info["groups"] == 1 and info["streams"] == 1, info
+    plan.launch()
+    torch.cuda.synchronize()
+    check(items, hosts, oracle_mod, "single group")
     plan.close()
 
 
