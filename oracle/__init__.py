@@ -11,7 +11,10 @@ it.  Two implementations live here:
   to pin the C++ oracle.
 
 Both follow the definition in the paper's "Core concepts" passage: the median
-is the element of zero-based rank (N-1)/2 of the window's values.
+is the element of zero-based rank (N-1)/2 of the window's values.  Any other
+rank, constant or given per pixel by a rank map (the Conclusion's percentile
+filtering, with the percentile free to vary across the image), is the same
+selection at that rank; a map entry outside [0, N) is clamped to it.
 """
 
 from __future__ import annotations
@@ -58,6 +61,8 @@ def _load():
         L = ctypes.c_longlong
         lib.oracle_filter.argtypes = [P, I, I, L, I, P, P, I, I, I, P, L, I]
         lib.oracle_filter_points.argtypes = [P, I, I, L, I, P, P, I, I, I, P, P, I, P, I]
+        lib.oracle_filter_rank_map.argtypes = [P, I, I, L, I, P, P, I, P, L, I, P, L, I]
+        lib.oracle_filter_points_ranks.argtypes = [P, I, I, L, I, P, P, I, P, I, P, P, I, P, I]
         lib.oracle_remap.argtypes = [I, I, I]
         lib.oracle_total_order_less.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         lib.oracle_ordinal_transform.argtypes = [P, I, I, P, P, P]
@@ -84,8 +89,12 @@ def _offsets(fp):
 
 
 def filter(img: np.ndarray, fp, boundary: str = "clamp", rank: int | None = None,
-           nthreads: int | None = None) -> np.ndarray:
-    """Rank-order filter a 2-D plane; fp is an (N, 2) array of (dx, dy) offsets."""
+           nthreads: int | None = None, rank_map: np.ndarray | None = None) -> np.ndarray:
+    """Rank-order filter a 2-D plane; fp is an (N, 2) array of (dx, dy) offsets.
+
+    rank_map (int32, same shape): a rank per output pixel, entries outside
+    [0, N) clamped to it (the window minimum or maximum); overrides `rank`.
+    """
     img = np.ascontiguousarray(img)
     if img.ndim != 2:
         raise ValueError("expected a 2-D plane")
@@ -95,17 +104,29 @@ def filter(img: np.ndarray, fp, boundary: str = "clamp", rank: int | None = None
     k = (n - 1) // 2 if rank is None else int(rank)
     out = np.empty_like(img)
     h, w = img.shape
-    rc = _load().oracle_filter(img.ctypes.data, w, h, w, DTYPE_CODE[dt], dx.ctypes.data,
-                               dy.ctypes.data, n, k, BOUNDARY_CODE[boundary], out.ctypes.data,
-                               w, nthreads or default_threads())
+    if rank_map is not None:
+        rm = np.ascontiguousarray(rank_map, dtype=np.int32)
+        if rm.shape != img.shape:
+            raise ValueError("rank_map must have the image's shape")
+        rc = _load().oracle_filter_rank_map(img.ctypes.data, w, h, w, DTYPE_CODE[dt],
+                                            dx.ctypes.data, dy.ctypes.data, n, rm.ctypes.data,
+                                            w, BOUNDARY_CODE[boundary], out.ctypes.data, w,
+                                            nthreads or default_threads())
+    else:
+        rc = _load().oracle_filter(img.ctypes.data, w, h, w, DTYPE_CODE[dt], dx.ctypes.data,
+                                   dy.ctypes.data, n, k, BOUNDARY_CODE[boundary],
+                                   out.ctypes.data, w, nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_filter rejected its arguments")
     return out
 
 
 def filter_points(img: np.ndarray, fp, xs, ys, boundary: str = "clamp",
-                  rank: int | None = None, nthreads: int | None = None) -> np.ndarray:
-    """Rank-order filter only at the listed pixels; returns a 1-D array."""
+                  rank: int | None = None, nthreads: int | None = None,
+                  ranks=None) -> np.ndarray:
+    """Rank-order filter only at the listed pixels; returns a 1-D array.
+    ranks: optional rank per listed pixel (clamped to [0, N)), overriding
+    `rank`."""
     img = np.ascontiguousarray(img)
     dt = dtype_name(img)
     dx, dy = _offsets(fp)
@@ -115,10 +136,22 @@ def filter_points(img: np.ndarray, fp, xs, ys, boundary: str = "clamp",
     ys = np.ascontiguousarray(np.asarray(ys, dtype=np.int32))
     vals = np.empty(len(xs), dtype=img.dtype)
     h, w = img.shape
-    rc = _load().oracle_filter_points(img.ctypes.data, w, h, w, DTYPE_CODE[dt], dx.ctypes.data,
-                                      dy.ctypes.data, n, k, BOUNDARY_CODE[boundary],
-                                      xs.ctypes.data, ys.ctypes.data, len(xs), vals.ctypes.data,
-                                      nthreads or default_threads())
+    if ranks is not None:
+        ks = np.ascontiguousarray(np.clip(np.asarray(ranks, dtype=np.int64),
+                                          -2**31, 2**31 - 1).astype(np.int32))
+        if ks.shape != xs.shape:
+            raise ValueError("one rank per listed pixel")
+        rc = _load().oracle_filter_points_ranks(img.ctypes.data, w, h, w, DTYPE_CODE[dt],
+                                                dx.ctypes.data, dy.ctypes.data, n,
+                                                ks.ctypes.data, BOUNDARY_CODE[boundary],
+                                                xs.ctypes.data, ys.ctypes.data, len(xs),
+                                                vals.ctypes.data, nthreads or default_threads())
+    else:
+        rc = _load().oracle_filter_points(img.ctypes.data, w, h, w, DTYPE_CODE[dt],
+                                          dx.ctypes.data, dy.ctypes.data, n, k,
+                                          BOUNDARY_CODE[boundary], xs.ctypes.data,
+                                          ys.ctypes.data, len(xs), vals.ctypes.data,
+                                          nthreads or default_threads())
     if rc != 0:
         raise ValueError("oracle_filter_points rejected its arguments")
     return vals
@@ -175,13 +208,16 @@ def _sort_keys_f32(vals: np.ndarray) -> np.ndarray:
 
 
 def tiny_filter(img: np.ndarray, fp, boundary: str = "clamp",
-                rank: int | None = None) -> np.ndarray:
-    """Full np.sort of every window.  Small images only (memory h*w*N)."""
+                rank: int | None = None, rank_map: np.ndarray | None = None) -> np.ndarray:
+    """Full np.sort of every window.  Small images only (memory h*w*N).
+    rank_map: a rank per pixel, clamped to [0, N)."""
     img = np.asarray(img)
     h, w = img.shape
     fp = np.asarray(fp).reshape(-1, 2)
     n = len(fp)
     k = (n - 1) // 2 if rank is None else int(rank)
+    if rank_map is not None:
+        k = np.clip(np.asarray(rank_map, dtype=np.int64), 0, n - 1)[:, :, None]
     ys = np.arange(h)[:, None, None] + fp[None, None, :, 1]
     xs = np.arange(w)[None, :, None] + fp[None, None, :, 0]
     ys = _np_remap(ys, h, boundary)
@@ -192,6 +228,13 @@ def tiny_filter(img: np.ndarray, fp, boundary: str = "clamp",
             raise ValueError("tiny_filter does not order NaN")
         keys = _sort_keys_f32(img)
         kwin = keys[np.broadcast_to(ys, (h, w, n)), np.broadcast_to(xs, (h, w, n))]
-        pos = np.argsort(kwin, axis=2, kind="stable")[:, :, k]
+        order = np.argsort(kwin, axis=2, kind="stable")
+        if rank_map is None:
+            pos = order[:, :, k]
+        else:
+            pos = np.take_along_axis(order, k, axis=2)[:, :, 0]
         return np.ascontiguousarray(np.take_along_axis(win, pos[:, :, None], axis=2)[:, :, 0])
-    return np.ascontiguousarray(np.sort(win, axis=2)[:, :, k])
+    srt = np.sort(win, axis=2)
+    if rank_map is None:
+        return np.ascontiguousarray(srt[:, :, k])
+    return np.ascontiguousarray(np.take_along_axis(srt, k, axis=2)[:, :, 0])

@@ -25,7 +25,10 @@
 //  * Float order: IEEE 754 totalOrder (-0 < +0; -NaN below -inf, +NaN above
 //    +inf).  The output is the input bit pattern of the selected element.
 //  * The rank is a parameter; the median is k = (N-1)/2 (lower median when N
-//    is even).
+//    is even).  A rank may also be given per output pixel (a rank map; the
+//    paper's Conclusion and its varying-percentile figure let the percentile
+//    vary across the image); a map entry outside [0, N) selects the nearest
+//    end (0 or N-1), i.e. the window minimum or maximum.
 //
 // Build: g++ -O3 -fopenmp -shared -fPIC (no -march=native: the library may
 // run on a different host CPU from the one that built it).
@@ -76,9 +79,9 @@ struct Args {
   int boundary;
 };
 
-// Median (rank-k element) of the window centred at (x, y); returns the bits.
+// Rank-k element of the window centred at (x, y); returns the bits.
 template <typename T>
-inline uint32_t window_rank(const Args& a, int x, int y, std::vector<T>& buf) {
+inline uint32_t window_rank(const Args& a, int x, int y, int k, std::vector<T>& buf) {
   const T* base = reinterpret_cast<const T*>(a.img);
   for (int i = 0; i < a.n; ++i) {
     const int sx = remap(x + a.dx[i], a.w, a.boundary);
@@ -86,33 +89,44 @@ inline uint32_t window_rank(const Args& a, int x, int y, std::vector<T>& buf) {
     buf[i] = base[(long long)sy * a.stride + sx];
   }
   if constexpr (sizeof(T) == 4) {
-    std::nth_element(buf.begin(), buf.begin() + a.rank, buf.end(), total_order_less);
+    std::nth_element(buf.begin(), buf.begin() + k, buf.end(), total_order_less);
   } else {
-    std::nth_element(buf.begin(), buf.begin() + a.rank, buf.end());
+    std::nth_element(buf.begin(), buf.begin() + k, buf.end());
   }
-  return (uint32_t)buf[a.rank];
+  return (uint32_t)buf[k];
 }
 
+// Rank map entry -> rank in [0, n).
+inline int clamp_rank(long long r, int n) { return r < 0 ? 0 : r >= n ? n - 1 : (int)r; }
+
+// Whole plane; the rank of pixel (x, y) is rank_map[y * rmap_stride + x]
+// (clamped) when rank_map is given, else a.rank.
 template <typename T>
-void filter_all(const Args& a, T* out, long long out_stride, int nthreads) {
+void filter_all(const Args& a, const int* rank_map, long long rmap_stride, T* out,
+                long long out_stride, int nthreads) {
 #pragma omp parallel num_threads(nthreads)
   {
     std::vector<T> buf(a.n);
 #pragma omp for schedule(dynamic, 1)
     for (int y = 0; y < a.h; ++y)
-      for (int x = 0; x < a.w; ++x)
-        out[(long long)y * out_stride + x] = (T)window_rank<T>(a, x, y, buf);
+      for (int x = 0; x < a.w; ++x) {
+        const int k = rank_map ? clamp_rank(rank_map[(long long)y * rmap_stride + x], a.n)
+                               : a.rank;
+        out[(long long)y * out_stride + x] = (T)window_rank<T>(a, x, y, k, buf);
+      }
   }
 }
 
+// Listed pixels; ks[i] (clamped) is pixel i's rank when ks is given.
 template <typename T>
-void filter_points(const Args& a, const int* xs, const int* ys, int npts, T* vals,
-                   int nthreads) {
+void filter_points(const Args& a, const int* xs, const int* ys, const int* ks, int npts,
+                   T* vals, int nthreads) {
 #pragma omp parallel num_threads(nthreads)
   {
     std::vector<T> buf(a.n);
 #pragma omp for schedule(dynamic, 64)
-    for (int i = 0; i < npts; ++i) vals[i] = (T)window_rank<T>(a, xs[i], ys[i], buf);
+    for (int i = 0; i < npts; ++i)
+      vals[i] = (T)window_rank<T>(a, xs[i], ys[i], ks ? clamp_rank(ks[i], a.n) : a.rank, buf);
   }
 }
 
@@ -134,9 +148,27 @@ int oracle_filter(const void* img, int w, int h, long long stride, int dtype,
   Args a{(const unsigned char*)img, w, h, stride, dtype, dx, dy, n, rank, boundary};
   if (check(a) || !out || out_stride < w) return -1;
   if (nthreads <= 0) nthreads = omp_get_max_threads();
-  if (dtype == DT_U8) filter_all<uint8_t>(a, (uint8_t*)out, out_stride, nthreads);
-  else if (dtype == DT_U16) filter_all<uint16_t>(a, (uint16_t*)out, out_stride, nthreads);
-  else filter_all<uint32_t>(a, (uint32_t*)out, out_stride, nthreads);
+  if (dtype == DT_U8) filter_all<uint8_t>(a, nullptr, 0, (uint8_t*)out, out_stride, nthreads);
+  else if (dtype == DT_U16)
+    filter_all<uint16_t>(a, nullptr, 0, (uint16_t*)out, out_stride, nthreads);
+  else filter_all<uint32_t>(a, nullptr, 0, (uint32_t*)out, out_stride, nthreads);
+  return 0;
+}
+
+// Filter a whole plane with a rank per pixel: rank_map (int32, row stride
+// rmap_stride elements); entries outside [0, n) are clamped to it.
+int oracle_filter_rank_map(const void* img, int w, int h, long long stride, int dtype,
+                           const int* dx, const int* dy, int n, const int* rank_map,
+                           long long rmap_stride, int boundary, void* out,
+                           long long out_stride, int nthreads) {
+  Args a{(const unsigned char*)img, w, h, stride, dtype, dx, dy, n, 0, boundary};
+  if (check(a) || !out || out_stride < w || !rank_map || rmap_stride < w) return -1;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  if (dtype == DT_U8)
+    filter_all<uint8_t>(a, rank_map, rmap_stride, (uint8_t*)out, out_stride, nthreads);
+  else if (dtype == DT_U16)
+    filter_all<uint16_t>(a, rank_map, rmap_stride, (uint16_t*)out, out_stride, nthreads);
+  else filter_all<uint32_t>(a, rank_map, rmap_stride, (uint32_t*)out, out_stride, nthreads);
   return 0;
 }
 
@@ -149,9 +181,28 @@ int oracle_filter_points(const void* img, int w, int h, long long stride, int dt
   for (int i = 0; i < npts; ++i)
     if (xs[i] < 0 || xs[i] >= w || ys[i] < 0 || ys[i] >= h) return -1;
   if (nthreads <= 0) nthreads = omp_get_max_threads();
-  if (dtype == DT_U8) filter_points<uint8_t>(a, xs, ys, npts, (uint8_t*)vals, nthreads);
-  else if (dtype == DT_U16) filter_points<uint16_t>(a, xs, ys, npts, (uint16_t*)vals, nthreads);
-  else filter_points<uint32_t>(a, xs, ys, npts, (uint32_t*)vals, nthreads);
+  if (dtype == DT_U8) filter_points<uint8_t>(a, xs, ys, nullptr, npts, (uint8_t*)vals, nthreads);
+  else if (dtype == DT_U16)
+    filter_points<uint16_t>(a, xs, ys, nullptr, npts, (uint16_t*)vals, nthreads);
+  else filter_points<uint32_t>(a, xs, ys, nullptr, npts, (uint32_t*)vals, nthreads);
+  return 0;
+}
+
+// As oracle_filter_points with a rank per listed pixel (ks[i], clamped to
+// [0, n)).
+int oracle_filter_points_ranks(const void* img, int w, int h, long long stride, int dtype,
+                               const int* dx, const int* dy, int n, const int* ks,
+                               int boundary, const int* xs, const int* ys, int npts,
+                               void* vals, int nthreads) {
+  Args a{(const unsigned char*)img, w, h, stride, dtype, dx, dy, n, 0, boundary};
+  if (check(a) || npts < 0 || (npts > 0 && (!xs || !ys || !vals || !ks))) return -1;
+  for (int i = 0; i < npts; ++i)
+    if (xs[i] < 0 || xs[i] >= w || ys[i] < 0 || ys[i] >= h) return -1;
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+  if (dtype == DT_U8) filter_points<uint8_t>(a, xs, ys, ks, npts, (uint8_t*)vals, nthreads);
+  else if (dtype == DT_U16)
+    filter_points<uint16_t>(a, xs, ys, ks, npts, (uint16_t*)vals, nthreads);
+  else filter_points<uint32_t>(a, xs, ys, ks, npts, (uint32_t*)vals, nthreads);
   return 0;
 }
 

@@ -344,3 +344,93 @@ def test_filter_points_matches_full(oracle_mod):
     xs = rng.integers(0, 96, 200)
     ys = rng.integers(0, 80, 200)
     assert np.array_equal(oracle_mod.filter_points(img, fp, xs, ys, "clamp"), full[ys, xs])
+
+
+# ------------------------------------------------------------ rank maps
+# A rank per output pixel (the percentile may vary across the image, paper
+# Conclusion and the varying-percentile figure); entries outside [0, N) are
+# clamped, i.e. select the window minimum or maximum.
+
+def _maps(n, w, h, seed):
+    return [workloads.random_ranks(w, h, n, seed), workloads.percentile_ramp(w, h, n)]
+
+
+def test_percentile_ramp_ends_and_monotone():
+    rm = workloads.percentile_ramp(11, 3, 49)
+    assert rm[:, 0].tolist() == [0, 0, 0] and rm[:, -1].tolist() == [48, 48, 48]
+    assert (np.diff(rm[0]) >= 0).all()
+    assert rm[0, 5] == 24                 # q = 1/2 -> the median rank (N - 1) / 2
+    assert workloads.percentile_ramp(1, 2, 7).tolist() == [[0], [0]]
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+@pytest.mark.parametrize("boundary", ["clamp", "mirror"])
+@pytest.mark.parametrize("fpname", ["disc1", "disc3", "ellipse", "triangle"])
+def test_rank_map_equals_full_sort(oracle_mod, dtype, boundary, fpname):
+    fp = SMALL_FPS[fpname]
+    n = len(fp)
+    for (w, h, seed) in [(13, 9, 1), (1, 7, 2), (6, 1, 3)]:
+        img = _img(dtype, w, h, seed)
+        for rm in _maps(n, w, h, seed):
+            got = oracle_mod.filter(img, fp, boundary, rank_map=rm)
+            exp = oracle_mod.tiny_filter(img, fp, boundary, rank_map=rm)
+            assert np.array_equal(got.view(np.uint8), exp.view(np.uint8)), (w, h)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+@pytest.mark.parametrize("boundary,mode", [("clamp", "nearest"), ("mirror", "mirror")])
+def test_rank_map_extremes_are_min_and_max_filters(oracle_mod, dtype, boundary, mode):
+    from scipy import ndimage
+    fp = F.ellipse(6, 2.5, 30)
+    n = len(fp)
+    R = int(np.abs(fp).max())
+    mask = np.zeros((2 * R + 1, 2 * R + 1), dtype=bool)
+    mask[fp[:, 1] + R, fp[:, 0] + R] = True
+    img = workloads.uniform(37, 23, dtype, 11)
+    if dtype == "f32":
+        img = (img * 2 - 1).astype(np.float32)
+        img[img == 0] = 0.5
+    rng = np.random.default_rng(0)
+    low = -rng.integers(0, 5, size=img.shape).astype(np.int32)          # 0 or below
+    high = (n - 1 + rng.integers(0, 5, size=img.shape)).astype(np.int32)  # N - 1 or above
+    assert np.array_equal(oracle_mod.filter(img, fp, boundary, rank_map=low),
+                          ndimage.minimum_filter(img, footprint=mask, mode=mode))
+    assert np.array_equal(oracle_mod.filter(img, fp, boundary, rank_map=high),
+                          ndimage.maximum_filter(img, footprint=mask, mode=mode))
+
+
+def test_rank_map_certificate(oracle_mod):
+    fp = F.regular_polygon(6, 5)
+    n = len(fp)
+    img = workloads.uniform(40, 30, "u16", 14)
+    rm = workloads.random_ranks(40, 30, n, 5)
+    out = oracle_mod.filter(img, fp, "mirror", rank_map=rm)
+    for y in range(0, 30, 2):
+        for x in range(0, 40, 3):
+            win = np.array([img[oracle_mod.remap(y + dy, 30, "mirror"),
+                                oracle_mod.remap(x + dx, 40, "mirror")] for dx, dy in fp])
+            k = min(max(int(rm[y, x]), 0), n - 1)
+            v = out[y, x]
+            assert (win < v).sum() <= k < (win <= v).sum(), (x, y, k)
+
+
+def test_rank_map_constant_equals_rank(oracle_mod):
+    fp = F.disc(3)
+    n = len(fp)
+    img = workloads.uniform(21, 17, "f32", 6)
+    for k in (0, 7, (n - 1) // 2, n - 1):
+        rm = np.full(img.shape, k, dtype=np.int32)
+        a = oracle_mod.filter(img, fp, "clamp", rank_map=rm)
+        b = oracle_mod.filter(img, fp, "clamp", rank=k)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), k
+
+
+def test_filter_points_ranks_match_rank_map(oracle_mod):
+    img = workloads.natural_u16(64, 48, seed=2)
+    fp = F.disc(5)
+    rm = workloads.random_ranks(64, 48, len(fp), 9)
+    full = oracle_mod.filter(img, fp, "mirror", rank_map=rm)
+    rng = np.random.default_rng(1)
+    xs, ys = rng.integers(0, 64, 150), rng.integers(0, 48, 150)
+    got = oracle_mod.filter_points(img, fp, xs, ys, "mirror", ranks=rm[ys, xs])
+    assert np.array_equal(got, full[ys, xs])

@@ -27,6 +27,12 @@ Workloads
 ``adversarial_u16``   high-frequency 0/65535 checkerboard inside a thick
                       border of mid-grey 32768 (the slow case the paper's
                       limitations section describes).
+``percentile_ramp``   int32 rank map for a window of N taps whose percentile
+                      runs from 0 % at the left column to 100 % at the right
+                      one (the paper's varying-percentile figure): q = x /
+                      (w - 1), rank = floor(q * (N - 1) + 1/2).
+``random_ranks``      int32 rank map, i.i.d. uniform over -3 .. N + 2 (a few
+                      entries outside [0, N) on purpose), seeded.
 """
 
 from __future__ import annotations
@@ -153,3 +159,17 @@ def special_floats(w: int, h: int, seed: int) -> np.ndarray:
     pick = rng.random((h, w)) < 0.5
     img[pick] = pool[rng.integers(0, len(pool), size=int(pick.sum()))]
     return img
+
+
+def percentile_ramp(w: int, h: int, taps: int) -> np.ndarray:
+    """Rank map whose percentile grows linearly from 0 (left) to 1 (right);
+    the percentile q becomes rank floor(q * (taps - 1) + 1/2)."""
+    q = np.arange(w, dtype=np.float64) / max(1, w - 1)
+    k = np.floor(q * (taps - 1) + 0.5).astype(np.int32)
+    return np.ascontiguousarray(np.broadcast_to(k[None, :], (h, w)))
+
+
+def random_ranks(w: int, h: int, taps: int, seed: int) -> np.ndarray:
+    """Rank map uniform over -3 .. taps + 2 (some entries out of range)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(-3, taps + 3, size=(h, w)).astype(np.int32)
