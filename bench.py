@@ -1,7 +1,7 @@
 """Benchmark: exact median filter, 4096x4096 uint16 natural-like image, disc r=32, clamp.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--radius R] [--size S]
-                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned]
+                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks]
                     [--weights PATH] [--copy-check]
 
 One step = one call of the plain filter over the whole image (every step of
@@ -11,15 +11,19 @@ JSON line.  The CPU-baseline leg times the brute-force oracle on a bounded
 sample of output pixels on the host cores and counts mismatches of the GPU
 output on that sample.
 
-Two comparison legs go into the same line:
+Three comparison legs go into the same line:
   batched  - 64 mixed images (w, h uniform in 128..2048, u8/u16/f32, disc
              r uniform in 1..64, clamp): one replay of the captured persistent
              launch against 64 sequential plain launches on one stream;
   learned  - 2048x2048 uint16 (i.i.d. uniform, and the natural-like
              generator), disc r = 16, 32, 64: CNN bracket proposal + bracketed
              tiles + exact fallback against the plain filter, with the
-             fallback rate.
-Both compare every output pixel with the plain filter's and a random sample
+             fallback rate;
+  ranks    - the headline image: 25/50/75 % percentile planes in one call
+             (one ordinal transform per tile) against three single-rank
+             calls, and a per-pixel rank map running 0..100 % across the
+             width against the median filter.
+Each compares every output pixel with the plain filter's and a random sample
 with the oracle.  --copy-check adds a 256 MiB device copy (three launches),
 whose hardware byte counters calibrate the filter's in a counter run.
 """
@@ -251,6 +255,58 @@ def leg_learned(torch, mf, weights, reps, check_oracle, log):
             "size": [S, S], "dtype": "u16", "results": rows}
 
 
+def leg_ranks(torch, mf, img, img_np, fp, ofp, reps, check_oracle, log):
+    """Headline image: 25/50/75 % percentile planes from one ordinal
+    transform per tile against three single-rank calls, and a rank map whose
+    percentile runs 0..100 % across the width against the median filter."""
+    import workloads
+    stream = torch.cuda.current_stream()
+    n = fp.taps
+    ks = [(n - 1) // 4, (n - 1) // 2, 3 * (n - 1) // 4]
+    singles = [torch.empty_like(img) for _ in ks]
+    multi = [torch.empty_like(img) for _ in ks]
+
+    def run_singles():
+        for k, o in zip(ks, singles):
+            mf.median_filter(img, fp, "clamp", out=o, rank=k)
+
+    run_singles()
+    mf.rank_filter(img, fp, ks, "clamp", outs=multi)
+    t_single = float(np.median(_time_events(torch, run_singles, stream, reps)))
+    t_multi = float(np.median(_time_events(
+        torch, lambda: mf.rank_filter(img, fp, ks, "clamp", outs=multi), stream, reps)))
+    mism = sum(int((a != b).sum()) for a, b in zip(singles, multi))
+    S_h, S_w = img_np.shape
+    rm_np = workloads.percentile_ramp(S_w, S_h, n)
+    rm = torch.from_numpy(rm_np).cuda()
+    ramp = torch.empty_like(img)
+    med = torch.empty_like(img)
+    mf.rank_map_filter(img, fp, rm, "clamp", out=ramp)
+    mf.median_filter(img, fp, "clamp", out=med)
+    t_ramp = float(np.median(_time_events(
+        torch, lambda: mf.rank_map_filter(img, fp, rm, "clamp", out=ramp), stream, reps)))
+    t_med = float(np.median(_time_events(
+        torch, lambda: mf.median_filter(img, fp, "clamp", out=med), stream, reps)))
+    cols = np.nonzero(rm_np[0] == (n - 1) // 2)[0]
+    ramp_np = ramp.cpu().numpy()
+    col_mism = int((ramp_np[:, cols] != med.cpu().numpy()[:, cols]).sum())
+    res = {"ranks": ks, "three_single_calls_ms": t_single, "one_three_plane_call_ms": t_multi,
+           "speedup": t_single / t_multi, "mismatches_multi_vs_single": mism,
+           "percentile_ramp_ms": t_ramp, "median_ms": t_med,
+           "ramp_median_columns_mismatches": col_mism}
+    if check_oracle:
+        import oracle
+        rng = np.random.default_rng(99)
+        xs, ys = rng.integers(0, S_w, 2000), rng.integers(0, S_h, 2000)
+        exp = oracle.filter_points(img_np, ofp, xs, ys, "clamp", ranks=rm_np[ys, xs],
+                                   nthreads=oracle.default_threads())
+        res["ramp_oracle_mismatches"] = int((ramp_np[ys, xs] != exp).sum())
+        res["ramp_oracle_checked_px"] = 2000
+    log(f"# ranks: 3 single {t_single:.2f} ms, one 3-plane call {t_multi:.2f} ms; "
+        f"ramp {t_ramp:.2f} ms vs median {t_med:.2f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,7 +316,7 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="plain,batched,learned")
+    ap.add_argument("--legs", default="plain,batched,learned,ranks")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
                                                       "bracket_net.npz"))
     ap.add_argument("--copy-check", action="store_true")
@@ -345,6 +401,11 @@ def main():
                if "batched" in legs else None)
     learned = (leg_learned(torch, mf, args.weights, 5, not args.no_cpu, log)
                if "learned" in legs else None)
+    if "ranks" in legs:
+        from oracle import footprints as OF
+        ranks = leg_ranks(torch, mf, img, img_np, fp, OF.disc(r), 5, not args.no_cpu, log)
+    else:
+        ranks = None
 
     cpu = None
     mismatches = None
@@ -367,13 +428,14 @@ def main():
         v1 = oracle.filter_points(img_np, ofp, xs1, ys1, "clamp", nthreads=cores)
         d1 = time.perf_counter() - c1
         mismatches = int((gpu_out[ys, xs] != v0).sum() + (gpu_out[ys1, xs1] != v1).sum())
-        # one thread on a 128x128 crop of output pixels, for scaling
-        cy, cx = np.mgrid[0:128, 0:128]
+        # one thread on a 512x512 crop of output pixels, for scaling
+        C = min(512, S)
+        cy, cx = np.mgrid[0:C, 0:C]
         c2 = time.perf_counter()
-        v2 = oracle.filter_points(img_np, ofp, cx.ravel() + S // 2, cy.ravel() + S // 2, "clamp",
-                                  nthreads=1)
+        x2, y2 = cx.ravel() + (S - C) // 2, cy.ravel() + (S - C) // 2
+        v2 = oracle.filter_points(img_np, ofp, x2, y2, "clamp", nthreads=1)
         d2 = time.perf_counter() - c2
-        mismatches += int((gpu_out[cy.ravel() + S // 2, cx.ravel() + S // 2] != v2).sum())
+        mismatches += int((gpu_out[y2, x2] != v2).sum())
         model = ""
         try:
             with open("/proc/cpuinfo") as f:
@@ -382,10 +444,11 @@ def main():
         except OSError:
             pass
         cpu = {"value": n1 / d1 / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
-               "cpu_model": model, "one_thread_mpx_s": 128 * 128 / d2 / 1e6,
+               "cpu_model": model, "one_thread_mpx_s": C * C / d2 / 1e6,
+               "one_thread_sample": f"central {C}x{C} crop, {d2:.1f}s",
                "sample": f"{n1} random output pixels of the same {S}x{S} image, disc r={r} "
                          f"({fp.taps} taps), brute force gather + nth_element, {d1:.1f}s",
-               "mismatches_vs_gpu": mismatches, "checked_px": n0 + n1 + 128 * 128}
+               "mismatches_vs_gpu": mismatches, "checked_px": n0 + n1 + C * C}
 
     line = {
         "metric": "Mpixel/s, r=32 disc uint16 4K, learned/batched vs plain GPU, bit-exact",
@@ -401,6 +464,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "learned": learned,
+        "ranks": ranks,
     }
     print(json.dumps(line))
 

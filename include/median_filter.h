@@ -124,6 +124,42 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * General rank outputs (paper, Discussion "Multi-Parameter Filtering": one
+ * ordinal transform can serve several percentiles; Conclusion and the
+ * varying-percentile figure: the percentile may change across the image).
+ *
+ * median_filter_ranks writes `nouts` planes (1..MF_MAX_RANK_OUTPUTS) from
+ * one pass: each tile's box is loaded and sorted once, then its bands run
+ * once per plane.  Plane q goes to outs[q].out (same shape and stride as
+ * img) and holds, at pixel (x, y), the window element of zero-based rank
+ *   rank_map[y * (rank_map_stride_bytes / 4) + x], clamped to [0, N - 1],
+ *   where outs[q].rank_map is not NULL (device int32 plane, w x h, stride a
+ *   multiple of 4 and >= 4 w), or
+ *   outs[q].rank (0 <= rank < N, else MF_ERR_INVALID_ARG) where it is NULL.
+ * A clamped entry below 0 selects the window minimum, one above N - 1 the
+ * maximum.  Each output must not overlap the image, another output or any
+ * rank map (MF_ERR_ALIAS); rank maps may overlap each other and the image.
+ * Asynchronous on `stream`, like median_filter.
+ *
+ * median_filter_rank_map = median_filter_ranks with one plane whose rank
+ * map is `rank_map` (not NULL).
+ * ------------------------------------------------------------------------ */
+#define MF_MAX_RANK_OUTPUTS 8
+typedef struct {
+  void* out;                    /* device plane */
+  int rank;                     /* used where rank_map is NULL */
+  const int* rank_map;          /* device int32 plane or NULL */
+  size_t rank_map_stride_bytes; /* row stride of rank_map */
+} mf_rank_output;
+
+int median_filter_ranks(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                        const mf_footprint* fp, int boundary, const mf_rank_output* outs,
+                        int nouts, hipStream_t stream);
+int median_filter_rank_map(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                           const mf_footprint* fp, int boundary, const int* rank_map,
+                           size_t rank_map_stride_bytes, void* out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched filtering (not in the paper): many images of any sizes, dtypes
  * and footprints in one persistent launch.
  *

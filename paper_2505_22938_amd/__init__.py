@@ -54,6 +54,8 @@ def lib():
         "mf_footprint_destroy": ([P], None),
         "median_filter": ([P, I, I, SZ, I, P, I, P, P], I),
         "median_filter_rank": ([P, I, I, SZ, I, P, I, I, P, P], I),
+        "median_filter_ranks": ([P, I, I, SZ, I, P, I, P, I, P], I),
+        "median_filter_rank_map": ([P, I, I, SZ, I, P, I, P, SZ, P, P], I),
         "mf_set_tile_override": ([I, I], I),
         "mf_query_plan": ([I, I, I, P, IP, IP, IP, IP, IP], I),
         "mf_work_counters": ([I, P], I),
@@ -234,6 +236,74 @@ def median_filter(img, fp: Footprint, boundary: str = "clamp", out=None, rank: i
                                   fp.handle, BOUNDARY[boundary], int(rank),
                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
         _check("median_filter_rank", rc)
+    return out
+
+
+MAX_RANK_OUTPUTS = 8
+
+
+class _RankOutput(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("rank", ctypes.c_int), ("rank_map", ctypes.c_void_p),
+                ("rank_map_stride_bytes", ctypes.c_size_t)]
+
+
+def rank_filter(img, fp: Footprint, ranks, boundary: str = "clamp", outs=None, stream=None):
+    """Several rank planes of `img` from one ordinal transform per tile.
+
+    `ranks` lists one entry per output plane: an int (a constant zero-based
+    rank in [0, N)) or a (h, w) int32 device tensor of per-pixel ranks
+    (clamped to [0, N - 1]).  Returns the list of output tensors (`outs`, if
+    given, must match `img` in shape, dtype and strides)."""
+    import torch
+    code, es, w, h, stride_bytes = _plane_args(img)
+    ranks = list(ranks)
+    if not 1 <= len(ranks) <= MAX_RANK_OUTPUTS:
+        raise ValueError(f"1..{MAX_RANK_OUTPUTS} rank planes per call")
+    if outs is None:
+        outs = [torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+                for _ in ranks]
+    if len(outs) != len(ranks):
+        raise ValueError("one output per rank entry")
+    arr = (_RankOutput * len(ranks))()
+    for q, (rk, o) in enumerate(zip(ranks, outs)):
+        if o.shape != img.shape or o.dtype != img.dtype or o.stride() != img.stride():
+            raise ValueError("outputs must match img in shape, dtype and strides")
+        if isinstance(rk, int):
+            arr[q] = _RankOutput(o.data_ptr(), int(rk), None, 0)
+        else:
+            if rk.dtype != torch.int32 or tuple(rk.shape) != (h, w) or not rk.is_cuda:
+                raise ValueError("a rank map is an int32 (h, w) device tensor")
+            if rk.stride(1) != 1:
+                raise ValueError("rank map rows must be contiguous")
+            arr[q] = _RankOutput(o.data_ptr(), 0, rk.data_ptr(),
+                                 rk.stride(0) * 4 if h > 1 else w * 4)
+    rc = lib().median_filter_ranks(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes, code,
+                                   fp.handle, BOUNDARY[boundary], ctypes.cast(arr, ctypes.c_void_p),
+                                   len(ranks), _stream_ptr(stream))
+    _check("median_filter_ranks", rc)
+    return outs
+
+
+def rank_map_filter(img, fp: Footprint, rank_map, boundary: str = "clamp", out=None,
+                    stream=None):
+    """One plane whose rank varies per pixel (int32 (h, w) device tensor,
+    clamped to [0, N - 1]); returns `out`."""
+    import torch
+    code, es, w, h, stride_bytes = _plane_args(img)
+    if out is None:
+        out = torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+    elif out.shape != img.shape or out.dtype != img.dtype or out.stride() != img.stride():
+        raise ValueError("out must match img in shape, dtype and strides")
+    if rank_map.dtype != torch.int32 or tuple(rank_map.shape) != (h, w) or not rank_map.is_cuda:
+        raise ValueError("a rank map is an int32 (h, w) device tensor")
+    if rank_map.stride(1) != 1:
+        raise ValueError("rank map rows must be contiguous")
+    rc = lib().median_filter_rank_map(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes, code,
+                                      fp.handle, BOUNDARY[boundary],
+                                      ctypes.c_void_p(rank_map.data_ptr()),
+                                      rank_map.stride(0) * 4 if h > 1 else w * 4,
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check("median_filter_rank_map", rc)
     return out
 
 

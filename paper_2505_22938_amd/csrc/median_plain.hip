@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kThreads) void mf_plain_gs_kernel(ImageDesc a) {
 
 namespace {
 
-using KernelFn = void (*)(ImageDesc);
+using KernelFn = PlainKernelFn;
 
 template <int KT, int SHAPE>
 KernelFn pick_imax(int imax) {
@@ -75,10 +75,11 @@ unsigned long long* g_counters = nullptr;  // device work counters, enabled on r
 
 unsigned long long* work_counters_ptr() { return g_counters; }
 
-// Launch one plain filter with a complete plan `a` (geometry + image bound).
+// Launch one plain filter with a complete plan `a` (geometry + image bound);
+// a.nq > 0 selects the general-rank kernels.
 int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream) {
   a.counters = g_counters;
-  KernelFn k = pick_kernel(a);
+  KernelFn k = a.nq > 0 ? pick_general_kernel(a) : pick_kernel(a);
   (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                             a.lds_bytes);
   const long long ntiles = (long long)a.tiles_x * a.tiles_y;

@@ -41,6 +41,8 @@ enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };
 
 // Everything one tile needs to know about its image and plan.  Passed by
 // value to the plain kernels and stored in the batched descriptor table.
+constexpr int kMaxRankOutputs = MF_MAX_RANK_OUTPUTS;   // planes of one general-rank call
+
 struct ImageDesc {
   const void* img;
   void* out;
@@ -69,6 +71,16 @@ struct ImageDesc {
   int br_cap;
   unsigned int* miss;
   unsigned int* miss_count;
+  // general ranks (kernels instantiated for them only): nq output planes
+  // from one ordinal transform per tile; plane q is written to outs[q] at
+  // rank ranks[q], or at the per-pixel rank rmaps[q][y * rmap_strides[q] +
+  // x] (int32, clamped to [0, rank_hi]) where rmaps[q] is set.  nq = 0: the
+  // single plane `out` at `rank`.
+  int nq, rank_hi;
+  void* outs[kMaxRankOutputs];
+  const int* rmaps[kMaxRankOutputs];
+  long long rmap_strides[kMaxRankOutputs];  // elements
+  int ranks[kMaxRankOutputs];
 };
 
 struct DeviceInfo {
@@ -110,6 +122,12 @@ int tune_cache_save(const char* path);
 
 // Device work counters of the plain engine (null when counting is off).
 unsigned long long* work_counters_ptr();
+
+// Plain-filter launch with a complete plan (median_plain.hip); a.nq > 0
+// runs the general-rank kernels (median_general.hip).
+using PlainKernelFn = void (*)(ImageDesc);
+int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream);
+PlainKernelFn pick_general_kernel(const ImageDesc& d);
 
 // Tile-shape override (measurement): 0 = off.
 void get_override(int* tw, int* th);

@@ -290,18 +290,18 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 }
 
 // Seed solve for the window centred at box (cx, cy): histogram of its
-// ordinals >> hshift, pick the bin holding rank k, refine by scanning.
+// ordinals >> hshift, pick the bin holding rank k (wave-uniform), refine by
+// scanning.
 // BR (bracketed tiles): ordinal 0 stands for every pixel below the bracket
 // and 0xffff for every pixel above it.  If the median is below (above) the
 // bracket, returns -1 with esc_p = 1 (T) and esc_c = the exact number of
 // window members below that ordinal, so sliding can go on from there.
 template <int KT, int SHAPE, bool BR, typename D>
-__device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, const D& a,
+__device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int k, const D& a,
                                           const uint16_t* om, const uint16_t* I, uint32_t* hist,
                                           const short2* rsp, int& blocks, int& esc_p,
                                           int& esc_c) {
   const int lane = threadIdx.x & 63;
-  const int k = a.rank;
   int zeros = 0;
   // 256 bins of 16-bit counts, two per word (a window has < 65536 taps).
   // Bracketed tiles: pixels below the bracket (ordinal 0) are counted in a
@@ -399,12 +399,25 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a,
 // Reverse map (paper, "Method Summary" step 7): the output is C[m].  For
 // bracketed tiles the stored key is relative to the bracket's low end lo.
 template <int KT, typename D>
-__device__ __forceinline__ void store_out(const D& a, int gx, int gy, const uint32_t* kbuf,
-                                          const uint16_t* crev, int m, uint32_t lo) {
+__device__ __forceinline__ void store_out(const D& a, void* out, int gx, int gy,
+                                          const uint32_t* kbuf, const uint16_t* crev, int m,
+                                          uint32_t lo) {
   const long long o = (long long)gy * a.stride + gx;
-  if (KT == KEY_U8) static_cast<uint8_t*>(a.out)[o] = (uint8_t)(crev[m] + lo);
-  if (KT == KEY_U16) static_cast<uint16_t*>(a.out)[o] = (uint16_t)(crev[m] + lo);
-  if (KT == KEY_F32) static_cast<uint32_t*>(a.out)[o] = key_to_f32(kbuf[m] + lo);
+  if (KT == KEY_U8) static_cast<uint8_t*>(out)[o] = (uint8_t)(crev[m] + lo);
+  if (KT == KEY_U16) static_cast<uint16_t*>(out)[o] = (uint16_t)(crev[m] + lo);
+  if (KT == KEY_F32) static_cast<uint32_t*>(out)[o] = key_to_f32(kbuf[m] + lo);
+}
+
+// Rank of output pixel (gx, gy) in plane q of the general form: the plane's
+// rank map entry clamped to [0, N) where the plane has a map and the pixel
+// is inside the image, else the plane's constant rank k0.
+template <bool GEN, typename D>
+__device__ __forceinline__ int rank_at(const D& a, int q, int k0, int gx, int gy, bool inside) {
+  if (!GEN) return k0;
+  const int* rm = a.rmaps[q];
+  if (!rm || !inside) return k0;
+  const int v = rm[(long long)gy * a.rmap_strides[q] + gx];
+  return min(max(v, 0), a.rank_hi);
 }
 
 // Bracketed tiles: append the flagged output pixels of the wave (index
@@ -455,10 +468,16 @@ __device__ __forceinline__ void br_sort(uint32_t* kbuf, int Ts, int passes, uint
 // pass) and the sweep goes on.  Returns true, with nothing written, if the
 // tile has more in-bracket pixels than region A holds (the caller then runs
 // the plain body on it); always false without BR.
-template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false, typename D>
+//
+// GEN (general ranks): the bands run once per output plane q < a.nq, each
+// writing a.outs[q] at a.ranks[q] or at the per-pixel ranks of a.rmaps[q],
+// all from the one ordinal transform of the tile (the paper's
+// multi-parameter and varying-percentile filtering).
+template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false, bool GEN = false, typename D>
 __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* smem,
                                           unsigned char* gslot) {
   static_assert(!(GS && BR), "bracketed tiles use the LDS variant");
+  static_assert(!(GEN && BR), "bracketed tiles compute the median only");
   const int T = a.T;
   unsigned char* abase = GS ? gslot : smem;   // region holding the sorted arrays
   uint32_t* kbuf = reinterpret_cast<uint32_t*>(abase);                // sort exchange / f32 C
@@ -746,7 +765,6 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   const long long clk1 = a.counters ? (long long)clock64() : 0;
 
   // 4. bands
-  const int k = a.rank;
   // seed histogram bins: ordinals >> hshift (bracketed tiles: sized to the
   // in-bracket ordinals)
   int hshift = a.hist_shift;
@@ -756,23 +774,12 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   }
   uint32_t* hist = hist_all + wid * 128;
   int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
-  long long seed_clk = 0;
+  long long seed_clk = 0, row_clk = 0, sweep_clk = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;
   const int seg = lane / tw, col = lane - seg * tw;
   const int band = wid * segs + seg;
   const int row0 = band * R;                 // first output row of this lane's band
   const int cxl = col - a.dx_min;            // lane's window centre, box coords
-  // Lane state after each row: its window's median ordinal m, and a pivot
-  // vp with the exact number vc of window members below it (vp = m, vc = k
-  // normally).  BR: a window whose median is outside the bracket is a miss
-  // (recomputed per pixel afterwards); its pivot is then the bracket end it
-  // left by (ordinal 1 or Tv) with the exact count there, so sliding goes on
-  // and the median is picked up again once it re-enters the bracket.
-  int m = 0, vp = 0, vc = k, miss = 0;
-
-  // 4a. seed + first row of each band, one segment at a time.  Windows
-  // outside the image are not computed: bands starting below it are
-  // skipped and the walk stops at the last column inside it.
   const int cols_in = min(tw, a.w - tx0);
   int4 hown = make_int4(0, 0, 0, 0);   // this lane's rows of hrow (lane, lane + 64)
   if (lane < a.nrows) {
@@ -783,17 +790,37 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     hown.z = hrow[lane + 64].x;
     hown.w = hrow[lane + 64].y;
   }
+  const int nq = GEN ? a.nq : 1;
+  for (int q = 0; q < nq; ++q) {
+  void* const outq = GEN ? a.outs[q] : a.out;
+  const int k0 = GEN ? a.ranks[q] : a.rank;
+  const long long clkq = GEN && a.counters ? (long long)clock64() : clk1;
+  // Lane state after each row: its window's selected ordinal m, and a pivot
+  // vp with the exact number vc of window members below it (vp = m, vc = the
+  // pixel's rank normally).  BR: a window whose median is outside the
+  // bracket is a miss (recomputed per pixel afterwards); its pivot is then
+  // the bracket end it left by (ordinal 1 or Tv) with the exact count there,
+  // so sliding goes on and the median is picked up again once it re-enters
+  // the bracket.
+  int m = 0, vp = 0, vc = k0, miss = 0;
+
+  // 4a. seed + first row of each band, one segment at a time.  Windows
+  // outside the image are not computed: bands starting below it are
+  // skipped and the walk stops at the last column inside it.
   for (int s = 0; s < segs; ++s) {
     const int brow = (wid * segs + s) * R;
     if (brow >= a.th || ty0 + brow >= a.h) break;   // band below the tile or the image
     const int cy = brow - a.dy_min;
+    // ranks of this row's pixels, lane c holding column c (general form)
+    const int krow = rank_at<GEN>(a, q, k0, tx0 + lane, ty0 + brow, lane < cols_in);
+    const int kseed = GEN ? __builtin_amdgcn_readfirstlane(krow) : k0;
     int ep = 0, ec = 0;
     const long long cs0 = a.counters ? (long long)clock64() : 0;
-    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, hshift, a, om, I, hist, rsp, blocks,
-                                       ep, ec);
+    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, hshift, kseed, a, om, I, hist, rsp,
+                                       blocks, ep, ec);
     if (a.counters) seed_clk += (long long)clock64() - cs0;
     ++seeds;
-    int hp = ms, hc = k;   // wave-uniform pivot and count
+    int hp = ms, hc = kseed;   // wave-uniform pivot and count
     if (BR && ms < 0) {
       hp = ep;
       hc = ec;
@@ -803,18 +830,19 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     vc = set_lane(hc, s * tw, vc);
     if (BR) miss = set_lane(ms < 0, s * tw, miss);
     for (int c = 1; c < cols_in; ++c) {
+      const int kc = GEN ? __builtin_amdgcn_readlane(krow, c) : k0;
       const int cxp = c - 1 - a.dx_min;
       const uint32_t pre_up = om[min(hp + lane, Tv - 1)];
       const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
       const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow, hown);
       int c_end = 0;
-      ms = scan_core<SHAPE>(hp, cnt_new, k, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
+      ms = scan_core<SHAPE>(hp, cnt_new, kc, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
                             om, rsp, blocks, pre_up, pre_dn, c_end);
       if (!BR || ms >= 0) {
         hp = ms;
-        hc = k;
+        hc = kc;
       } else {
-        hp = cnt_new <= k ? Tv : 1;
+        hp = cnt_new <= kc ? Tv : 1;
         hc = c_end;
       }
       m = set_lane(ms, s * tw + c, m);
@@ -828,7 +856,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   {
     const int gx = tx0 + col, gy = ty0 + row0;
     const bool own = lane < segs * tw && col < cols_in && row0 < a.th && gy < a.h;
-    if (own && !miss) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    if (own && !miss) store_out<KT>(a, outq, gx, gy, kbuf, crev, m, blo);
     if (BR) push_misses(a, own && miss, gx, gy);
   }
 
@@ -840,6 +868,8 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, rows_lim - wid * segs * R)));
   for (int r = 1; r < r_end; ++r) {
     const bool lane_active = in_cols && r < rows_in;
+    const int gx = tx0 + col, gy = ty0 + row0 + r;
+    const int kl = rank_at<GEN>(a, q, k0, gx, gy, lane_active);
     const int cy_prev = row0 + r - 1 - a.dy_min;
     const int lbase = cy_prev * a.pitch + cxl;
     int delta = 0;
@@ -854,7 +884,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     int mnew = m, esc = 0;
     const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
     if (lane_active) {
-      mnew = lane_select<SHAPE>(pl, cl, k, cxy, kLaneBudget, Tv, a, om, rsp, groups);
+      mnew = lane_select<SHAPE>(pl, cl, kl, cxy, kLaneBudget, Tv, a, om, rsp, groups);
       if (BR && mnew < 0 && (pl <= 0 || pl >= Tv)) {
         // walked off an end of the bracket: a miss
         esc = 1;
@@ -867,12 +897,13 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       left &= left - 1;
       const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
       const int plL = __builtin_amdgcn_readlane(pl, L), clL = __builtin_amdgcn_readlane(cl, L);
+      const int kL = GEN ? __builtin_amdgcn_readlane(kl, L) : k0;
       int c_end = 0;
-      const int mL = scan_select<KT, SHAPE>(plL, clL, k, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
+      const int mL = scan_select<KT, SHAPE>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
                                             rsp, blocks, c_end);
       mnew = set_lane(mL, L, mnew);
       if (BR && mL < 0) {
-        pl = set_lane(clL <= k ? Tv : 1, L, pl);
+        pl = set_lane(clL <= kL ? Tv : 1, L, pl);
         cl = set_lane(c_end, L, cl);
         esc = set_lane(1, L, esc);
       }
@@ -881,23 +912,27 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       if (!BR || !esc) {
         m = mnew;
         vp = mnew;
-        vc = k;
+        vc = kl;
       } else {
         vp = pl;
         vc = cl;
       }
     }
-    const int gx = tx0 + col, gy = ty0 + row0 + r;
-    if (lane_active && !esc) store_out<KT>(a, gx, gy, kbuf, crev, m, blo);
+    if (lane_active && !esc) store_out<KT>(a, outq, gx, gy, kbuf, crev, m, blo);
     if (BR) push_misses(a, lane_active && esc, gx, gy);
   }
-  if (a.counters && lane == 0) {
+  if (a.counters) {
     const long long clk3 = (long long)clock64();
+    row_clk += clk2 - clkq;
+    sweep_clk += clk3 - clk2;
+  }
+  }  // planes
+  if (a.counters && lane == 0) {
     atomicAdd(&a.counters[CNT_BLOCKS], (unsigned long long)blocks);
     atomicAdd(&a.counters[CNT_SEEDS], (unsigned long long)seed_taps);
     atomicAdd(&a.counters[CNT_CYC_SORT], (unsigned long long)(clk1 - clk0));
-    atomicAdd(&a.counters[CNT_CYC_ROW], (unsigned long long)(clk2 - clk1));
-    atomicAdd(&a.counters[CNT_CYC_SWEEP], (unsigned long long)(clk3 - clk2));
+    atomicAdd(&a.counters[CNT_CYC_ROW], (unsigned long long)row_clk);
+    atomicAdd(&a.counters[CNT_CYC_SWEEP], (unsigned long long)sweep_clk);
     atomicAdd(&a.counters[CNT_WAVES], 1ull);
     atomicAdd(&a.counters[CNT_CYC_SEED], (unsigned long long)seed_clk);
     atomicAdd(&a.counters[CNT_CYC_LOAD], (unsigned long long)(clk_load - clk0));
