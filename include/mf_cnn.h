@@ -113,12 +113,13 @@ int mf_learned_train_step(mf_learned* net, const void* img, const void* median, 
                           size_t stride_bytes, int dtype, int radius, float lr, float* loss,
                           hipStream_t stream);
 
-/* Tile grid the learned and bracketed filters use for this image (tile
- * size as mf_query_plan reports it), and the most in-bracket box pixels a
- * tile can rank (a tile with more is recomputed whole by the plain engine).
- * Any output pointer may be NULL. */
+/* Tile grid the learned and bracketed filters use for this image: tile
+ * counts, the output tile size (the tallest default shape; it may differ
+ * from the plain filter's choice, mf_query_plan), and the most in-bracket
+ * box pixels a tile can rank (a tile with more is recomputed whole by the
+ * plain engine).  Any output pointer may be NULL. */
 int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
-                         int* tiles_y, int* bracket_capacity);
+                         int* tiles_y, int* bracket_capacity, int* tile_w, int* tile_h);
 
 /* Exact median filter of an 8/16-bit plane with caller-supplied per-tile
  * value brackets: tile_brackets (device) holds (lo, hi) pairs of unsigned

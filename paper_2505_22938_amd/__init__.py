@@ -90,7 +90,7 @@ def lib():
         "mf_learned_forward": ([P, P, I, I, SZ, I, I, P, P], I),
         "mf_learned_train_step": ([P, P, P, I, I, SZ, I, I, ctypes.c_float,
                                    ctypes.POINTER(ctypes.c_float), P], I),
-        "mf_learned_tile_grid": ([I, I, I, P, IP, IP, IP], I),
+        "mf_learned_tile_grid": ([I, I, I, P, IP, IP, IP, IP, IP], I),
         "median_filter_bracketed": ([P, I, I, SZ, I, P, I, P, P, P,
                                      ctypes.POINTER(ctypes.c_ulonglong), P], I),
         "median_filter_learned": ([P, I, I, SZ, I, P, I, P, P,
@@ -581,8 +581,17 @@ class LearnedNet:
         _check("mf_learned_tile_grid", lib().mf_learned_tile_grid(w, h, dtype, fp.handle,
                                                                   ctypes.byref(tx),
                                                                   ctypes.byref(ty),
-                                                                  ctypes.byref(cap)))
+                                                                  ctypes.byref(cap), None, None))
         return (tx.value, ty.value, cap.value) if with_capacity else (tx.value, ty.value)
+
+    @staticmethod
+    def tile_shape(w: int, h: int, dtype: int, fp: Footprint):
+        """(tile_w, tile_h) of the bracketed filters' output tiles."""
+        tw, th = ctypes.c_int(), ctypes.c_int()
+        _check("mf_learned_tile_grid", lib().mf_learned_tile_grid(w, h, dtype, fp.handle, None,
+                                                                  None, None, ctypes.byref(tw),
+                                                                  ctypes.byref(th)))
+        return tw.value, th.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and _lib is not None:

@@ -428,7 +428,7 @@ int learned_plan(int dtype, const mf_footprint* fp, LearnedPlan* lp) {
   int rc = mf::device_info(lp->dev, &lp->di);
   if (rc) return rc;
   mf::ImageDesc base{};
-  if ((rc = mf::choose_plan(dtype, fp, lp->di.lds_max, 33, &base))) return rc;
+  if ((rc = mf::choose_plan_tall(dtype, fp, lp->di.lds_max, 33, &base))) return rc;
   if ((rc = mf::make_plan_br(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->br)))
     return rc;
   if (mf::make_plan(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->fb) != MF_OK ||
@@ -718,7 +718,7 @@ int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, in
 }
 
 int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* tiles_x,
-                         int* tiles_y, int* bracket_capacity) {
+                         int* tiles_y, int* bracket_capacity, int* tile_w, int* tile_h) {
   if (!fp || w <= 0 || h <= 0 || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
   LearnedPlan lp;
   const int rc = learned_plan(dtype, fp, &lp);
@@ -726,6 +726,8 @@ int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* t
   if (tiles_x) *tiles_x = (w + lp.br.tw - 1) / lp.br.tw;
   if (tiles_y) *tiles_y = (h + lp.br.th - 1) / lp.br.th;
   if (bracket_capacity) *bracket_capacity = lp.br.br_cap;
+  if (tile_w) *tile_w = lp.br.tw;
+  if (tile_h) *tile_h = lp.br.th;
   return MF_OK;
 }
 

@@ -104,7 +104,7 @@ int median_filter_ranks(const void* img, int w, int h, size_t stride_bytes, int 
   const void* table = nullptr;
   if ((rc = footprint_device_table(fp, dev, &table))) return rc;
   ImageDesc a{};
-  if ((rc = choose_plan(dtype, fp, di.lds_max, 33, &a))) return rc;
+  if ((rc = choose_plan(dtype, fp, di.lds_max, 33, &a, w, h, di.cus))) return rc;
   bind_image(&a, img, w, h, stride_bytes, dtype, fp, boundary, (fp->taps - 1) / 2, table);
   a.out = outs[0].out;
   a.nq = nouts;

@@ -109,18 +109,21 @@ int launch_plain(const void* img, int w, int h, size_t stride_bytes, int dtype,
   rc = footprint_device_table(fp, dev, &table);
   if (rc) return rc;
   ImageDesc a{};
-  rc = choose_plan(dtype, fp, di.lds_max, 33, &a);
+  rc = choose_plan(dtype, fp, di.lds_max, 33, &a, w, h, di.cus);
   if (rc) return rc;
   bind_image(&a, img, w, h, stride_bytes, dtype, fp, boundary, rank, table);
   a.out = out;
   return launch_with_plan(a, dev, di, stream);
 }
 
-int query_plan(int dtype, const mf_footprint* fp, ImageDesc* d) {
+int query_plan(int w, int h, int dtype, const mf_footprint* fp, ImageDesc* d) {
   int dev = 0;
   DeviceInfo di;
-  if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &di) != MF_OK) di.lds_max = 160 * 1024;
-  return choose_plan(dtype, fp, di.lds_max, 33, d);
+  if (hipGetDevice(&dev) != hipSuccess || device_info(dev, &di) != MF_OK) {
+    di.lds_max = 160 * 1024;
+    di.cus = 256;
+  }
+  return choose_plan(dtype, fp, di.lds_max, 33, d, w, h, di.cus);
 }
 
 int set_counters(int enable) {
@@ -183,11 +186,10 @@ int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
 
 int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, int* tile_h,
                   int* box_w, int* box_h, int* lds) {
-  (void)w;
-  (void)h;
-  if (!fp || (dtype != MF_U8 && dtype != MF_U16 && dtype != MF_F32)) return MF_ERR_INVALID_ARG;
+  if (!fp || w < 0 || h < 0 || (dtype != MF_U8 && dtype != MF_U16 && dtype != MF_F32))
+    return MF_ERR_INVALID_ARG;
   mf::ImageDesc d{};
-  const int rc = mf::query_plan(dtype, fp, &d);
+  const int rc = mf::query_plan(w, h, dtype, fp, &d);
   if (rc) return rc;
   if (tile_w) *tile_w = d.tw;
   if (tile_h) *tile_h = d.th;

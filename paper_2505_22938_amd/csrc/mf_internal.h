@@ -95,7 +95,13 @@ int device_info(int dev, DeviceInfo* out);
 // that fits, LDS first; imax_cap bounds the register capacity of LDS plans.
 int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
 int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, ImageDesc* d);
-int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d);
+// w, h, cus (image size and compute units, 0 = unknown) let the default
+// choice keep enough tiles per CU.  choose_plan_tall: the override or the
+// tallest default shape, ignoring the tuned table (bracketed tiles).
+int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d,
+                int w = 0, int h = 0, int cus = 0);
+int choose_plan_tall(int dtype, const mf_footprint* fp, int lds_max, int imax_cap,
+                     ImageDesc* d);
 // Bracketed-tile plan (8/16-bit keys) for a given shape: region A holds only
 // the in-bracket pixels (up to br_cap of them), region B the ordinal image
 // of the whole box.  MF_ERR_UNSUPPORTED if fewer than 1024 fit.

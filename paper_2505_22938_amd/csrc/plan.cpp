@@ -232,50 +232,103 @@ int best_gs_plan(int dtype, const mf_footprint* fp, int lds_max, ImageDesc* d) {
   return MF_OK;
 }
 
-int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d) {
-  int tw = 0, th = 0;
-  get_override(&tw, &th);
-  if (tw > 0) return plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d);
-  if (tuned_shape(dtype, fp, &tw, &th) &&
-      plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d) == MF_OK)
-    return MF_OK;
-  // the first LDS shape that fits (widest, tallest first), unless a
-  // global-scratch shape re-reads far fewer box pixels per output pixel
-  // (small LDS tiles under large windows).  Measured crossover: the
-  // global-scratch plan wins once the LDS plan's amplification is about 1.8x
-  // as high for 8/16-bit keys, 2.5x for float keys (64-bit words, 8 passes)
-  static const int tws[] = {64, 32, 16, 8};
+// Tallest output tile for the default choice, by the window's extent e (its
+// largest offset from the centre).  Small windows hold few members among
+// the box's ordinals, so the omnigram walks between neighbouring outputs
+// get longer as the box grows; measured on 2048^2 and 4096^2 images of
+// every key type (smooth and i.i.d. content), the best heights are about
+// 16 (e <= 1), 32 (e <= 3), 48 (e <= 5), 64 (e <= 16) and the tallest that
+// fits beyond.
+static int default_th_cap(const mf_footprint* fp) {
+  const int e = std::max(std::max(fp->dx_max, -fp->dx_min), std::max(fp->dy_max, -fp->dy_min));
+  if (e <= 1) return 16;
+  if (e <= 3) return 32;
+  if (e <= 5) return 48;
+  if (e <= 16) return 64;
+  return 128;
+}
+
+// The first LDS shape that fits (widest, then tallest first, heights up to
+// th_cap), unless a global-scratch shape re-reads far fewer box pixels per
+// output pixel (small LDS tiles under large windows).  Measured crossover:
+// the global-scratch plan wins once the LDS plan's amplification is about
+// 1.8x as high for 8/16-bit keys, 2.5x for float keys (64-bit words, 8
+// passes).  fill_tiles > 0: among 64-wide shapes, step down in height (not
+// below 64) while the image would have fewer tiles than that (fewer tiles
+// per CU than needed to balance tiles of uneven cost).
+static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, int th_cap,
+                        int w, int h, long long fill_tiles, ImageDesc* d) {
   ImageDesc gs{};
   const bool have_gs = best_gs_plan(dtype, fp, lds_max, &gs) == MF_OK;
-  for (int w : tws) {
-    const int segs = 64 / w;
-    for (int R = 8; R >= 1; R /= 2)
-      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, d) == MF_OK && d->imax <= imax_cap) {
-        const double amp = (double)d->T / ((double)d->tw * d->th);
-        const double amp_gs = have_gs ? (double)gs.T / ((double)gs.tw * gs.th) : 1e300;
-        if (amp > (dtype == MF_F32 ? 2.5 : 1.8) * amp_gs) *d = gs;
-        return MF_OK;
+  auto finish = [&](ImageDesc* c) {
+    const double amp = (double)c->T / ((double)c->tw * c->th);
+    const double amp_gs = have_gs ? (double)gs.T / ((double)gs.tw * gs.th) : 1e300;
+    if (amp > (dtype == MF_F32 ? 2.5 : 1.8) * amp_gs) *c = gs;
+    return MF_OK;
+  };
+  // 64 wide, heights in steps of 16
+  for (int th = th_cap; th >= 16; th -= 16) {
+    if (make_plan(dtype, fp, lds_max, 64, th, d) != MF_OK || d->imax > imax_cap) continue;
+    if (fill_tiles > 0) {
+      for (int t2 = th - 16; t2 >= 64; t2 -= 16) {
+        const long long tiles = (long long)((w + 63) / 64) * ((h + d->th - 1) / d->th);
+        if (tiles >= fill_tiles) break;
+        ImageDesc c{};
+        if (make_plan(dtype, fp, lds_max, 64, t2, &c) == MF_OK && c.imax <= imax_cap) *d = c;
       }
+    }
+    return finish(d);
+  }
+  // narrower tiles for windows whose 64-wide boxes do not fit
+  static const int tws[] = {32, 16, 8};
+  for (int tw : tws) {
+    const int segs = 64 / tw;
+    for (int R = 8; R >= 1; R /= 2)
+      if (make_plan(dtype, fp, lds_max, tw, kWaves * segs * R, d) == MF_OK && d->imax <= imax_cap)
+        return finish(d);
   }
   if (!have_gs) return MF_ERR_UNSUPPORTED;
   *d = gs;
   return MF_OK;
 }
 
+int choose_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, ImageDesc* d,
+                int w, int h, int cus) {
+  int tw = 0, th = 0;
+  get_override(&tw, &th);
+  if (tw > 0) return plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d);
+  if (tuned_shape(dtype, fp, &tw, &th) &&
+      plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d) == MF_OK)
+    return MF_OK;
+  const long long fill = w > 0 && h > 0 && cus > 0 ? 4LL * cus : 0;
+  return default_plan(dtype, fp, lds_max, imax_cap, default_th_cap(fp), w, h, fill, d);
+}
+
+int choose_plan_tall(int dtype, const mf_footprint* fp, int lds_max, int imax_cap,
+                     ImageDesc* d) {
+  int tw = 0, th = 0;
+  get_override(&tw, &th);
+  if (tw > 0) return plan_shape(dtype, fp, lds_max, imax_cap, tw, th, d);
+  return default_plan(dtype, fp, lds_max, imax_cap, 128, 0, 0, 0, d);
+}
+
 std::vector<ImageDesc> candidate_plans(int dtype, const mf_footprint* fp, int lds_max,
                                        int imax_cap) {
   std::vector<ImageDesc> out;
   static const int tws[] = {64, 32, 16, 8};
+  auto add = [&](int w, int th) {
+    ImageDesc d{};
+    if (make_plan(dtype, fp, lds_max, w, th, &d) == MF_OK && d.imax <= imax_cap)
+      out.push_back(d);
+    else if (make_plan_gs(dtype, fp, lds_max, w, th, &d) == MF_OK)
+      out.push_back(d);
+  };
   for (int w : tws) {
     const int segs = 64 / w;
-    for (int R = 1; R <= 16; R *= 2) {
-      ImageDesc d{};
-      if (make_plan(dtype, fp, lds_max, w, kWaves * segs * R, &d) == MF_OK && d.imax <= imax_cap)
-        out.push_back(d);
-      else if (make_plan_gs(dtype, fp, lds_max, w, kWaves * segs * R, &d) == MF_OK)
-        out.push_back(d);
-    }
+    for (int R = 1; R <= 16; R *= 2) add(w, kWaves * segs * R);
   }
+  add(64, 48);
+  add(64, 96);
   ImageDesc g{};
   if (best_gs_plan(dtype, fp, lds_max, &g) == MF_OK) {
     bool seen = false;

@@ -105,9 +105,8 @@ def train(images=512, size=512, radii=(16, 32, 64), epochs=2, lr=3e-3, holdout=1
                 mf.LearnedNet.tile_grid(size, size, mf.MF_U16, fps[r])
             except mf.MedianFilterError:
                 continue   # no bracketed plan for this footprint
-            p = mf.query_plan(size, size, mf.MF_U16, fps[r])
-            need.append(tile_margins(cells.cpu().numpy(), med.cpu().numpy(), p["tile_w"],
-                                     p["tile_h"]))
+            tw, th = mf.LearnedNet.tile_shape(size, size, mf.MF_U16, fps[r])
+            need.append(tile_margins(cells.cpu().numpy(), med.cpu().numpy(), tw, th))
     need = np.concatenate(need) if need else np.zeros(1)
     margin = float(np.quantile(need, 1.0 - fail_target))
     log(f"# margin {margin:.5f} (quantile {1 - fail_target:.3f} of {need.size} held-out tiles)")

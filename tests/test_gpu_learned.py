@@ -36,8 +36,9 @@ def dev(a):
 
 def tile_info(mf, w, h, dtype_code, fp):
     tx, ty = mf.LearnedNet.tile_grid(w, h, dtype_code, fp)
-    p = mf.query_plan(w, h, dtype_code, fp)
-    return tx, ty, p["tile_w"], p["tile_h"]
+    tw, th = mf.LearnedNet.tile_shape(w, h, dtype_code, fp)
+    assert tx == -(-w // tw) and ty == -(-h // th)
+    return tx, ty, tw, th
 
 
 def brackets_dev(br):
