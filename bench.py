@@ -1,7 +1,7 @@
 """Benchmark: exact median filter, 4096x4096 uint16 natural-like image, disc r=32, clamp.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--radius R] [--size S]
-                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks]
+                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks,stress]
                     [--weights PATH] [--copy-check]
 
 One step = one call of the plain filter over the whole image (every step of
@@ -11,7 +11,7 @@ JSON line.  The CPU-baseline leg times the brute-force oracle on a bounded
 sample of output pixels on the host cores and counts mismatches of the GPU
 output on that sample.
 
-Three comparison legs go into the same line:
+Comparison legs in the same line:
   batched  - 64 mixed images (w, h uniform in 128..2048, u8/u16/f32, disc
              r uniform in 1..64, clamp): one replay of the captured persistent
              launch against 64 sequential plain launches on one stream;
@@ -22,7 +22,9 @@ Three comparison legs go into the same line:
   ranks    - the headline image: 25/50/75 % percentile planes in one call
              (one ordinal transform per tile) against three single-rank
              calls, and a per-pixel rank map running 0..100 % across the
-             width against the median filter.
+             width against the median filter;
+  stress   - the slow input of the paper's limitations discussion (1024^2
+             0/65535 checkerboard in a mid-grey frame, r=32), reported only.
 Each compares every output pixel with the plain filter's and a random sample
 with the oracle.  --copy-check adds a 256 MiB device copy (three launches),
 whose hardware byte counters calibrate the filter's in a counter run.
@@ -307,6 +309,36 @@ def leg_ranks(torch, mf, img, img_np, fp, ofp, reps, check_oracle, log):
     return res
 
 
+def leg_stress(torch, mf, reps, check_oracle, log):
+    """1024x1024 uint16 0/65535 checkerboard inside a mid-grey frame, disc
+    r=32: the input the paper's limitations discussion describes as slow
+    (medians jump across the whole value range between neighbours).
+    Reported, not a target."""
+    import workloads
+    from oracle import footprints as OF
+    img_np = workloads.adversarial_u16(1024, 1024, border=96)
+    img = torch.from_numpy(img_np).cuda()
+    out = torch.empty_like(img)
+    fp = mf.Footprint.disc(32)
+    mf.median_filter(img, fp, "clamp", out=out)
+    ts = _time_events(torch, lambda: mf.median_filter(img, fp, "clamp", out=out),
+                      torch.cuda.current_stream(), reps)
+    mf.work_counters(1)
+    mf.median_filter(img, fp, "clamp", out=out)
+    torch.cuda.synchronize()
+    c = mf.work_counters(-1)
+    mf.work_counters(0)
+    ms = float(np.median(ts))
+    res = {"image": "1024x1024 u16 checkerboard 0/65535 in a 96-px frame of 32768",
+           "radius": 32, "ms": ms, "mpx_s": 1024 * 1024 / 1e3 / ms,
+           "scan_blocks_per_px": c[0] / (1024 * 1024), "lane_groups_per_px": c[6] / (1024 * 1024)}
+    if check_oracle:
+        res["oracle_mismatches"] = _oracle_sample(img_np, OF.disc(32), out.cpu().numpy(), 2000, 5)
+        res["oracle_checked_px"] = 2000
+    log(f"# stress: adversarial 1024^2 r=32 {ms:.3f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,7 +348,7 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="plain,batched,learned,ranks")
+    ap.add_argument("--legs", default="plain,batched,learned,ranks,stress")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
                                                       "bracket_net.npz"))
     ap.add_argument("--copy-check", action="store_true")
@@ -380,9 +412,12 @@ def main():
     wm = work_model(plan, fp.taps, rows, cols, S, S, 4, blocks, seeds, groups)
     kmean = float(np.mean(kern_ms))
     achieved = wm["total"] / (kmean * 1e-3)
+    traffic = measured_traffic() if (S, r) == (4096, 32) else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Top/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-                "traffic": measured_traffic() if (S, r) == (4096, 32) else None, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "hbm_gb_s": traffic / (kmean * 1e-3) / 1e9 if traffic else None,
+                "hbm_frac_of_8tb_s": traffic / (kmean * 1e-3) / 8e12 if traffic else None,
                 "kernel_ms_mean": kmean, "kernel_ms_min": float(np.min(kern_ms)),
                 "work_lane_ops": wm, "clocks_per_wave": phase_clk}
     gpu_out = out.cpu().numpy()
@@ -406,6 +441,7 @@ def main():
         ranks = leg_ranks(torch, mf, img, img_np, fp, OF.disc(r), 5, not args.no_cpu, log)
     else:
         ranks = None
+    stress = leg_stress(torch, mf, 5, not args.no_cpu, log) if "stress" in legs else None
 
     cpu = None
     mismatches = None
@@ -465,6 +501,7 @@ def main():
         "batched": batched,
         "learned": learned,
         "ranks": ranks,
+        "stress": stress,
     }
     print(json.dumps(line))
 
