@@ -206,8 +206,8 @@ static int plan_shape(int dtype, const mf_footprint* fp, int lds_max, int imax_c
 // lanes and half of the waves busy in the band phase.  Widths need not
 // divide 64 (a wave then owns one band and some lanes sit out).
 int best_gs_plan(int dtype, const mf_footprint* fp, int lds_max, ImageDesc* d) {
-  static const int tws[] = {64, 56, 54, 48, 32, 16};
-  static const int ths[] = {128, 112, 96, 80, 64, 56, 54, 48, 32, 16};
+  static const int tws[] = {64, 56, 54, 48, 32, 16, 8};
+  static const int ths[] = {128, 112, 96, 80, 64, 56, 54, 48, 32, 16, 8};
   double best = 1e300;
   ImageDesc pick{};
   bool found = false;

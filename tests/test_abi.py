@@ -151,3 +151,12 @@ def test_default_tile_height_follows_window_and_image_size():
     assert (q(4096, 32)["tile_w"], q(4096, 32)["tile_h"]) == (64, 128)
     assert (q(2048, 32)["tile_w"], q(2048, 32)["tile_h"]) == (64, 64)   # 1024 tiles
     assert q(2048, 32, mf.MF_F32)["tile_h"] == 64
+
+
+def test_largest_window_plans():
+    """Radius 123 (width 247) is the largest window the filter plans; 124 is
+    refused."""
+    p = mf.query_plan(500, 500, mf.MF_U16, mf.Footprint.disc(123))
+    assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (8, 8, 254, 254)
+    with pytest.raises(mf.MedianFilterError):
+        mf.query_plan(500, 500, mf.MF_U16, mf.Footprint.disc(124))

@@ -224,3 +224,12 @@ def test_lognormal_f32_full_size_sampled(mf, oracle_mod, name):
     ys = rng.integers(0, 2160, 3000)
     exp = oracle_mod.filter_points(img, b(), xs, ys, "mirror")
     assert np.array_equal(got[ys, xs].view(np.uint32), exp.view(np.uint32))
+
+
+@pytest.mark.parametrize("dt,r,w,h", [("u8", 123, 41, 29), ("f32", 118, 37, 23), ("u16", 110, 70, 45)])
+def test_plain_largest_windows(mf, oracle_mod, dt, r, w, h):
+    """Windows up to the largest the 8-bit box coordinates allow (width 247,
+    radius 123: 8x8 output tiles under a 254x254 box in global scratch)."""
+    img = workloads.uniform(w, h, dt, r) if dt != "f32" else workloads.special_floats(w, h, r)
+    got = run(mf, img, mf.Footprint.disc(r), "mirror")
+    assert_same(got, oracle_mod.filter(img, OF.disc(r), "mirror"), f"{dt} r={r}")
