@@ -47,29 +47,32 @@ if ROOT not in sys.path:
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T int32 VALU lane-ops/s
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 
-# Sources the plain kernel and its launch plan are built from.
-PLAIN_SOURCES = ("tile_engine.h", "tile_common.h", "mf_internal.h", "median_plain.hip",
-                 "plan.cpp")
+# Sources the plain kernel is built from; with the launch plan (tile, box,
+# LDS bytes) they determine the kernel's memory traffic.
+PLAIN_SOURCES = ("tile_engine.h", "tile_common.h", "mf_internal.h", "median_plain.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
                             "mf_plain_kernel_u16_4096x4096_disc_r32_hbm_bytes.md")
 
 
-def kernel_sources_hash():
+def kernel_sources_hash(plan):
     import hashlib
     h = hashlib.sha256()
     for name in PLAIN_SOURCES:
         with open(os.path.join(ROOT, "paper_2505_22938_amd", "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
+    geo = [plan[k] for k in ("tile_w", "tile_h", "box_w", "box_h", "lds_bytes")]
+    h.update(("plan:" + ",".join(str(v) for v in geo)).encode())
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(plan):
     """HBM bytes per launch from the committed counter summary, or None when
-    the kernel sources changed since the counters were taken."""
+    the kernel sources or the launch plan changed since the counters were
+    taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l)
-        if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_hash():
+        if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_hash(plan):
             return None
         return int(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -412,7 +415,7 @@ def main():
     wm = work_model(plan, fp.taps, rows, cols, S, S, 4, blocks, seeds, groups)
     kmean = float(np.mean(kern_ms))
     achieved = wm["total"] / (kmean * 1e-3)
-    traffic = measured_traffic() if (S, r) == (4096, 32) else None
+    traffic = measured_traffic(plan) if (S, r) == (4096, 32) else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Top/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
