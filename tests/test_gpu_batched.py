@@ -190,3 +190,24 @@ def test_batched_full_mixed_batch_sampled(mf, oracle_mod):
         exp = oracle_mod.filter_points(img_np, OF.disc(sp["radius"]), xs, ys, "clamp")
         assert np.array_equal(got[ys, xs].view(np.uint8), exp.view(np.uint8)), (i, sp)
     plan.close()
+
+
+def test_batched_degenerate_images(mf, oracle_mod):
+    """Empty planes, 1-pixel planes and single rows/columns beside ordinary
+    ones in one plan: the empty ones are skipped, the rest equal the oracle."""
+    shapes = [(0, 7), (5, 0), (1, 1), (1, 9), (13, 1), (40, 33)]
+    items, exp = [], []
+    for i, (w, h) in enumerate(shapes):
+        img = workloads.uniform(max(w, 1), max(h, 1), "u16", 70 + i)[:h, :w]
+        d = torch.from_numpy(np.ascontiguousarray(img)).cuda() if w and h else \
+            torch.empty((h, w), dtype=torch.uint16, device="cuda")
+        items.append((d, torch.empty_like(d), mf.Footprint.disc(3), "mirror"))
+        exp.append(oracle_mod.filter(img, OF.disc(3), "mirror") if w and h else None)
+    plan = mf.BatchPlan(items)
+    assert plan.info()["tiles"] > 0
+    plan.launch()
+    torch.cuda.synchronize()
+    for (d, out, _, _), e in zip(items, exp):
+        if e is not None:
+            assert np.array_equal(out.cpu().numpy(), e), d.shape
+    plan.close()
