@@ -54,8 +54,8 @@ struct ImageDesc {
   int rank, limit;
   int segs, band_rows, hist_shift;
   const short2* spans;  // nrows row spans (index dy - dy_min) then ncols column spans
-  // LDS layout, bytes
-  int off_p, off_C, off_B, off_hist, off_tab, lds_bytes;
+  // LDS layout, bytes (off_I: the ordinal image)
+  int off_p, off_C, off_B, off_I, off_hist, off_tab, lds_bytes;
   unsigned long long* counters;  // optional work counters (null: off)
   // global-scratch variant: per-workgroup slot of slot_bytes at scratch
   unsigned char* scratch;

@@ -99,21 +99,31 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
       break;
     }
   if (!im) return MF_ERR_UNSUPPORTED;
-  // region A: sort exchange (u32 words); afterwards omega and C (8/16-bit
-  // keys: two 16-bit arrays of T + 16 padding entries each) or C32 + omega
-  // (float keys).  Region B: digit counts during the sort, afterwards the
-  // ordinal image and the per-wave seed histograms.
+  // Region A: the sort exchange (u32 words; float keys: u32 keys, then a
+  // 16-bit payload array).  After the sort it holds the omnigram (T + 16
+  // padding entries, 16-bit) and the ordinal image, which takes the part of
+  // the exchange buffer the omnigram leaves free.  The reverse map is not
+  // kept: an output reads its value back from the image at the omnigram's
+  // location.  Region B: digit counts during the sort, then the per-wave
+  // seed histograms.
   const int TP = round_up(T, 8) + 16;
-  const int kb = dtype == MF_F32 ? 4 * (round_up(T, 4) + 4) : 4 * TP;
-  const int pb = dtype == MF_F32 ? 2 * TP : 0;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
   const int hb = kWaves * 128 * 4;
-  const int B = std::max(kCounterBytes, ib + hb);
-  d->off_p = kb;
-  d->off_C = 2 * TP;
-  d->off_B = kb + pb;
-  d->off_hist = d->off_B + ib;
-  d->off_tab = d->off_B + B;
+  int A;
+  if (dtype == MF_F32) {
+    const int kb = std::max(4 * (round_up(T, 4) + 4), ib);   // keys, then the ordinal image
+    d->off_p = kb;                                          // payload = omnigram
+    d->off_I = 0;
+    A = kb + 2 * TP;
+  } else {
+    d->off_p = 0;
+    d->off_I = 2 * TP;                                      // after the omnigram
+    A = std::max(4 * TP, 2 * TP + ib);
+  }
+  d->off_C = 0;
+  d->off_B = A;
+  d->off_hist = A;
+  d->off_tab = A + std::max(kCounterBytes, hb);
   d->lds_bytes = d->off_tab + table_bytes(d);
   d->kt = dtype;
   d->gs = 0;
@@ -144,6 +154,7 @@ int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   d->off_p = 0;
   d->off_C = 2 * TPc;
   d->off_B = 4 * TPc;
+  d->off_I = d->off_B;
   d->off_hist = d->off_B + ib;
   d->off_tab = d->off_B + B;
   d->lds_bytes = d->off_tab + tb;
@@ -179,6 +190,7 @@ int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   d->slot_bytes = round_up(2 * wb * TP, 256);
   d->ipt = (T + kThreads - 1) / kThreads;
   d->off_B = 0;
+  d->off_I = 0;
   d->off_hist = ib;
   d->off_tab = B;
   d->lds_bytes = B + table_bytes(d);
@@ -252,8 +264,9 @@ static int default_th_cap(const mf_footprint* fp) {
 // th_cap), unless a global-scratch shape re-reads far fewer box pixels per
 // output pixel (small LDS tiles under large windows).  Measured crossover:
 // the global-scratch plan wins once the LDS plan's amplification is about
-// 1.8x as high for 8/16-bit keys, 2.5x for float keys (64-bit words, 8
-// passes).  fill_tiles > 0: among 64-wide shapes, step down in height (not
+// twice as high (4096^2 uint16: radius 52-60 run 11-30 % faster in LDS
+// tiles up to that ratio, radius 64 is 18 % faster in global scratch; float
+// keys, 64-bit words and 8 passes, cross over at the same ratio).  fill_tiles > 0: among 64-wide shapes, step down in height (not
 // below 64) while the image would have fewer tiles than that (fewer tiles
 // per CU than needed to balance tiles of uneven cost).
 static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, int th_cap,
@@ -263,7 +276,7 @@ static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax
   auto finish = [&](ImageDesc* c) {
     const double amp = (double)c->T / ((double)c->tw * c->th);
     const double amp_gs = have_gs ? (double)gs.T / ((double)gs.tw * gs.th) : 1e300;
-    if (amp > (dtype == MF_F32 ? 2.5 : 1.8) * amp_gs) *c = gs;
+    if (amp > 2.0 * amp_gs) *c = gs;
     return MF_OK;
   };
   // 64 wide, heights in steps of 16
@@ -272,7 +285,7 @@ static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax
     if (fill_tiles > 0) {
       for (int t2 = th - 16; t2 >= 64; t2 -= 16) {
         const long long tiles = (long long)((w + 63) / 64) * ((h + d->th - 1) / d->th);
-        if (tiles >= fill_tiles) break;
+        if (tiles * 20 >= fill_tiles * 19) break;   // within 5 % of the target
         ImageDesc c{};
         if (make_plan(dtype, fp, lds_max, 64, t2, &c) == MF_OK && c.imax <= imax_cap) *d = c;
       }

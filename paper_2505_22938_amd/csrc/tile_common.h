@@ -81,10 +81,11 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // Output: with PAYLOAD (float keys) the last pass writes the sorted keys to
 // kout[dst] and the payload to omega[dst].  Without PAYLOAD the element is
 // one word key << 16 | loc; the last pass splits it into loc -> omega[dst]
-// and key -> crev[dst].  kbuf/pbuf are the exchange buffers of earlier
+// and key -> crev[dst].  KEEP_C = false writes only omega (the caller reads
+// values back from the image through the omnigram's locations).  kbuf/pbuf are the exchange buffers of earlier
 // passes; the output arrays may alias them (the last pass reads only
 // registers).
-template <int ITEMS, bool PAYLOAD>
+template <int ITEMS, bool PAYLOAD, bool KEEP_C = true>
 __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
                                                  int T, int shift0, int passes,
                                                  uint32_t* kbuf, uint16_t* pbuf,
@@ -150,14 +151,14 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
             kbuf[dst] = key[i];
             pbuf[dst] = pos[i];
           } else {
-            kout[dst] = key[i];
+            if (KEEP_C) kout[dst] = key[i];
             omega[dst] = pos[i];
           }
         } else if (pass + 1 < passes) {
           kbuf[dst] = key[i];
         } else {
           omega[dst] = (uint16_t)key[i];
-          crev[dst] = (uint16_t)(key[i] >> 16);
+          if (KEEP_C) crev[dst] = (uint16_t)(key[i] >> 16);
         }
       }
     }

@@ -396,16 +396,31 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a,
   return delta;
 }
 
-// Reverse map (paper, "Method Summary" step 7): the output is C[m].  For
+// Reverse map (paper, "Method Summary" step 7): the output is C[m], the
+// value of ordinal m.  GATHER (tiles sorted in LDS): no copy of C is kept;
+// the value is read back from the image at the omnigram's box location of
+// m through the boundary map, which yields exactly the bits the sort saw.
+// Otherwise C is read from crev (16-bit keys) or kbuf (float keys); for
 // bracketed tiles the stored key is relative to the bracket's low end lo.
-template <int KT, typename D>
+template <int KT, bool GATHER, typename D>
 __device__ __forceinline__ void store_out(const D& a, void* out, int gx, int gy,
-                                          const uint32_t* kbuf, const uint16_t* crev, int m,
-                                          uint32_t lo) {
+                                          const uint32_t* kbuf, const uint16_t* crev,
+                                          const uint16_t* om, int m, uint32_t lo, int gx0,
+                                          int gy0) {
   const long long o = (long long)gy * a.stride + gx;
-  if (KT == KEY_U8) static_cast<uint8_t*>(out)[o] = (uint8_t)(crev[m] + lo);
-  if (KT == KEY_U16) static_cast<uint16_t*>(out)[o] = (uint16_t)(crev[m] + lo);
-  if (KT == KEY_F32) static_cast<uint32_t*>(out)[o] = key_to_f32(kbuf[m] + lo);
+  if constexpr (GATHER) {
+    const uint32_t loc = om[m];
+    const int sx = remap(gx0 + (int)(loc & 255u), a.w, a.boundary);
+    const int sy = remap(gy0 + (int)(loc >> 8), a.h, a.boundary);
+    const long long src = (long long)sy * a.stride + sx;
+    if (KT == KEY_U8) static_cast<uint8_t*>(out)[o] = static_cast<const uint8_t*>(a.img)[src];
+    if (KT == KEY_U16) static_cast<uint16_t*>(out)[o] = static_cast<const uint16_t*>(a.img)[src];
+    if (KT == KEY_F32) static_cast<uint32_t*>(out)[o] = static_cast<const uint32_t*>(a.img)[src];
+  } else {
+    if (KT == KEY_U8) static_cast<uint8_t*>(out)[o] = (uint8_t)(crev[m] + lo);
+    if (KT == KEY_U16) static_cast<uint16_t*>(out)[o] = (uint16_t)(crev[m] + lo);
+    if (KT == KEY_F32) static_cast<uint32_t*>(out)[o] = key_to_f32(kbuf[m] + lo);
+  }
 }
 
 // Rank of output pixel (gx, gy) in plane q of the general form: the plane's
@@ -485,7 +500,8 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   uint16_t* om = KT == KEY_F32 ? pbuf : reinterpret_cast<uint16_t*>(abase);   // omnigram
   uint16_t* crev = reinterpret_cast<uint16_t*>(abase + a.off_C);      // u8/u16 reverse map
   uint16_t* cnt = reinterpret_cast<uint16_t*>(smem + a.off_B);
-  uint16_t* I = reinterpret_cast<uint16_t*>(smem + a.off_B);
+  uint16_t* I = reinterpret_cast<uint16_t*>(smem + a.off_I);
+  constexpr bool GATHER = !GS && !BR;   // no reverse map in LDS (store_out)
   uint32_t* hist_all = reinterpret_cast<uint32_t*>(smem + a.off_hist);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + a.off_tab);
   const int nr4 = (a.nrows + 3) & ~3;
@@ -707,11 +723,11 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     // 2. ordinal transform
     const int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
     if (KT == KEY_F32)
-      block_radix_sort<IMAX, true>(key, pos, T, 0, passes, kbuf, pbuf, om, nullptr, kbuf, cnt,
-                                   wsum);
+      block_radix_sort<IMAX, true, false>(key, pos, T, 0, passes, kbuf, pbuf, om, nullptr,
+                                          nullptr, cnt, wsum);
     else
-      block_radix_sort<IMAX, false>(key, pos, T, 16, passes, kbuf, pbuf, om, crev, nullptr, cnt,
-                                    wsum);
+      block_radix_sort<IMAX, false, false>(key, pos, T, 16, passes, kbuf, pbuf, om, nullptr,
+                                           nullptr, cnt, wsum);
   } else {
     // load the box straight into global scratch as (key << 16 | location)
     // words: 32-bit for 8/16-bit keys, 64-bit for float keys
@@ -856,7 +872,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   {
     const int gx = tx0 + col, gy = ty0 + row0;
     const bool own = lane < segs * tw && col < cols_in && row0 < a.th && gy < a.h;
-    if (own && !miss) store_out<KT>(a, outq, gx, gy, kbuf, crev, m, blo);
+    if (own && !miss) store_out<KT, GATHER>(a, outq, gx, gy, kbuf, crev, om, m, blo, gx0, gy0);
     if (BR) push_misses(a, own && miss, gx, gy);
   }
 
@@ -918,7 +934,8 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
         vc = cl;
       }
     }
-    if (lane_active && !esc) store_out<KT>(a, outq, gx, gy, kbuf, crev, m, blo);
+    if (lane_active && !esc)
+      store_out<KT, GATHER>(a, outq, gx, gy, kbuf, crev, om, m, blo, gx0, gy0);
     if (BR) push_misses(a, lane_active && esc, gx, gy);
   }
   if (a.counters) {

@@ -130,27 +130,30 @@ def test_tile_override_validation_and_general_shapes():
 
 def test_large_window_plans_minimise_amplification():
     """Radius 100: the box of a 54x56 tile (254x256) is the largest that fits
-    the 8-bit box coordinates; beyond radius 48 small LDS tiles give way to
-    tall global-scratch tiles (radius 48 still fits a 64x48 LDS tile whose
-    amplification is close enough)."""
+    the 8-bit box coordinates; LDS tiles up to twice the global-scratch
+    plan's amplification (radius 48: 64x96, radius 56: 64x64), tall
+    global-scratch tiles beyond (radius 64)."""
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(100))
     assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (54, 56, 254, 256)
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(48))
-    assert (p["tile_w"], p["tile_h"]) == (64, 48), p
-    for r in (56, 64):
-        p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(r))
-        assert p["tile_w"] * p["tile_h"] >= 64 * 96, (r, p)
+    assert (p["tile_w"], p["tile_h"]) == (64, 96), p
+    p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(56))
+    assert (p["tile_w"], p["tile_h"]) == (64, 64), p
+    p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(64))
+    assert p["tile_w"] * p["tile_h"] >= 64 * 96 and p["lds_bytes"] < 120000, p
 
 
 def test_default_tile_height_follows_window_and_image_size():
     """Small windows take short tiles (shorter omnigram walks), 64 rows up to
     a window extent of 16, the tallest fitting tile beyond, stepped down to
-    keep at least 4 tiles per compute unit on small images."""
+    keep about 4 tiles per compute unit on small images."""
     q = lambda s, r, dt=mf.MF_U16: mf.query_plan(s, s, dt, mf.Footprint.disc(r))  # noqa: E731
     assert [q(4096, r)["tile_h"] for r in (1, 2, 3, 4, 5, 8, 16)] == [16, 32, 32, 48, 48, 64, 64]
     assert (q(4096, 32)["tile_w"], q(4096, 32)["tile_h"]) == (64, 128)
     assert (q(2048, 32)["tile_w"], q(2048, 32)["tile_h"]) == (64, 64)   # 1024 tiles
     assert q(2048, 32, mf.MF_F32)["tile_h"] == 64
+    p = mf.query_plan(3840, 2160, mf.MF_F32, mf.Footprint.disc(24))   # 1020 tiles: close enough
+    assert (p["tile_w"], p["tile_h"]) == (64, 128), p
 
 
 def test_largest_window_plans():

@@ -104,7 +104,7 @@ def test_batched_groups_on_forked_streams(mf, oracle_mod):
     capacities) run as separate groups spread over forked streams: eager
     launches on a side stream and on the current stream, and graph replays
     with eager work between them, all equal the oracle."""
-    cases = [("u8", 90, 64, 3), ("u16", 150, 120, 60), ("f32", 100, 70, 12),
+    cases = [("u8", 90, 64, 3), ("u16", 150, 120, 64), ("f32", 100, 70, 12),
              ("u16", 200, 40, 20), ("u8", 33, 250, 30), ("f32", 64, 64, 40)]
     items, hosts = [], []
     for i, (dt, w, h, r) in enumerate(cases):
