@@ -233,3 +233,28 @@ def test_plain_largest_windows(mf, oracle_mod, dt, r, w, h):
     img = workloads.uniform(w, h, dt, r) if dt != "f32" else workloads.special_floats(w, h, r)
     got = run(mf, img, mf.Footprint.disc(r), "mirror")
     assert_same(got, oracle_mod.filter(img, OF.disc(r), "mirror"), f"{dt} r={r}")
+
+
+def test_autotune_records_shape_and_cache_round_trip(mf, oracle_mod, tmp_path):
+    """The autotuner times the candidate shapes on the caller's image, records
+    the fastest for (dtype, footprint); later calls and plan queries use it,
+    outputs stay exact, and the table survives a JSON save / load."""
+    import json
+    img = workloads.natural_u16(300, 210, seed=8)
+    fp, ofp = mf.Footprint.ellipse(7.5, 4, 10), OF.ellipse(7.5, 4, 10)   # used by no other test
+    d = to_dev(img)
+    tw, th, ms = mf.autotune(d, fp, "mirror", reps=2)
+    assert 1 <= tw <= 64 and th >= 1 and ms > 0
+    p = mf.query_plan(300, 210, mf.MF_U16, fp)
+    assert (p["tile_w"], p["tile_h"]) == (tw, th)
+    got = mf.median_filter(d, fp, "mirror")
+    torch.cuda.synchronize()
+    assert_same(got.cpu().numpy(), oracle_mod.filter(img, ofp, "mirror"), "tuned shape")
+    path = str(tmp_path / "tune.json")
+    mf.tune_cache_save(path)
+    entries = json.load(open(path))
+    mine = [e for e in entries if (e["tile_w"], e["tile_h"]) == (tw, th)]
+    assert mine and all(set(e) == {"key", "tile_w", "tile_h", "ms"} for e in entries)
+    mf.tune_cache_load(path)
+    assert (mf.query_plan(300, 210, mf.MF_U16, fp)["tile_w"],
+            mf.query_plan(300, 210, mf.MF_U16, fp)["tile_h"]) == (tw, th)
