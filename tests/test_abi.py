@@ -163,3 +163,37 @@ def test_largest_window_plans():
     assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (8, 8, 254, 254)
     with pytest.raises(mf.MedianFilterError):
         mf.query_plan(500, 500, mf.MF_U16, mf.Footprint.disc(124))
+
+
+def test_rank_outputs_argument_validation_is_host_side():
+    """median_filter_ranks / median_filter_rank_map reject bad arguments
+    before any GPU work (fake device addresses are never touched)."""
+    L = mf.lib()
+    fp = mf.Footprint.disc(2)          # 13 taps
+    P = ctypes.c_void_p
+    img, o1, o2, rm = 4096, 1 << 20, 1 << 21, 1 << 22
+
+    def outs(*specs):
+        arr = (mf._RankOutput * max(1, len(specs)))()
+        for i, (out, rank, rmap, stride) in enumerate(specs):
+            arr[i] = mf._RankOutput(out, rank, rmap, stride)
+        return ctypes.cast(arr, ctypes.c_void_p), len(specs)
+
+    def call(specs, n=None, w=8, h=8):
+        a, k = outs(*specs)
+        return L.median_filter_ranks(P(img), w, h, 8, 0, fp.handle, 0, a, k if n is None else n,
+                                     None)
+
+    assert call([(o1, 6, None, 0)], n=0) == -1                       # no planes
+    assert call([(o1, 6, None, 0)] * 9) == -1                        # more than 8
+    assert call([(o1, 13, None, 0)]) == -1                           # rank >= N
+    assert call([(o1, -1, None, 0)]) == -1                           # rank < 0
+    assert call([(o1, 0, rm, 28)]) == -1                             # map stride < 4 w
+    assert call([(o1, 0, rm, 34)]) == -1                             # not a multiple of 4
+    assert call([(o1, 0, None, 0), (o1, 1, None, 0)]) == -2          # two planes, one buffer
+    assert call([(img + 8, 0, None, 0)]) == -2                       # output overlaps image
+    assert call([(o1, 0, o1 + 4, 32)]) == -2                         # map overlaps an output
+    assert call([(None, 0, None, 0)]) == -1                          # null output
+    assert call([(o1, 6, None, 0)], w=0) == 0                        # empty image: no work
+    assert L.median_filter_rank_map(P(img), 8, 8, 8, 0, fp.handle, 0, None, 32, P(o1),
+                                    None) == -1                      # null rank map
