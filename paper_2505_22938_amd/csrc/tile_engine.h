@@ -130,6 +130,15 @@ __device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, con
   }
 }
 
+// A 16-bit LDS load the compiler keeps where it is written (a volatile
+// access in the LDS address space), so a prefetch is not sunk into the path
+// that consumes it.  Only for arrays in LDS (OM_LDS: not the global-scratch
+// omnigram of large boxes).
+__device__ __forceinline__ uint32_t lds_load_early(const uint16_t* base, int i) {
+  using lds_u16 = const volatile __attribute__((address_space(3))) uint16_t;
+  return *((lds_u16*)base + i);
+}
+
 // Rank selection for one window (wave-uniform arguments): given a pivot
 // ordinal p and the number c of window members with ordinal < p, return the
 // member ordinal m with exactly k members below it.  The omnigram is tested
@@ -144,7 +153,7 @@ __device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, con
 // possible when some pixels are outside the omnigram, see BR below); c_end
 // then receives the number of members below the end reached (below T going
 // up, below ordinal 0 going down).
-template <int SHAPE, typename D>
+template <int SHAPE, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int T,
                                          const D& a, const uint16_t* om,
                                          const short2* rsp, int& blocks, uint32_t pre_up,
@@ -156,8 +165,12 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
     int b = p;
     uint32_t cur = pre_up;
     for (int it = 0; it < cap && b < T; ++it, b += 64) {
-      const uint32_t nxt = om[min(max(b + 64 + lane, 0), T - 1)];
-      const bool in = b + lane < T &&
+      // next block's entry, loaded before this block is tested (volatile:
+      // the load stays here instead of sinking into the continue path)
+      const int ni = min(max(b + 64 + lane, 0), T - 1);
+      const uint32_t nxt = OM_LDS ? lds_load_early(om, ni) : (uint32_t)om[ni];
+      // both tests evaluated (no branch): cur is always a loaded entry
+      const bool in = (b + lane < T) &
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
       const uint64_t mask = wave_ballot(in);
       const int pc = __popcll(mask);
@@ -177,9 +190,10 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
     int b = p;
     uint32_t cur = pre_dn;
     for (int it = 0; it < cap && b > 0; ++it, b -= 64) {
-      const uint32_t nxt = om[max(b - 128 + lane, 0)];
+      const int ni = max(b - 128 + lane, 0);
+      const uint32_t nxt = OM_LDS ? lds_load_early(om, ni) : (uint32_t)om[ni];
       const int v = b - 64 + lane;
-      const bool in = v >= 0 && v < T &&
+      const bool in = (v >= 0) & (v < T) &
                       member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
       const uint64_t mask = wave_ballot(in);
       const int pc = __popcll(mask);
@@ -199,7 +213,7 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
   return -1;
 }
 
-template <int KT, int SHAPE, typename D>
+template <int KT, int SHAPE, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, int T,
                                            const D& a, const uint16_t* om,
                                            const short2* rsp, int& blocks, int& c_end) {
@@ -207,7 +221,7 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, 
   const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
   const bool up = c <= k;
   const uint32_t pre = up ? om[min(max(p + lane, 0), T - 1)] : om[max(p - 64 + lane, 0)];
-  return scan_core<SHAPE>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre, c_end);
+  return scan_core<SHAPE, OM_LDS>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre, c_end);
 }
 
 // Lane-parallel rank selection: every lane refines its own window.  Same
@@ -296,7 +310,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 // and 0xffff for every pixel above it.  If the median is below (above) the
 // bracket, returns -1 with esc_p = 1 (T) and esc_c = the exact number of
 // window members below that ordinal, so sliding can go on from there.
-template <int KT, int SHAPE, bool BR, typename D>
+template <int KT, int SHAPE, bool BR, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int k, const D& a,
                                           const uint16_t* om, const uint16_t* I, uint32_t* hist,
                                           const short2* rsp, int& blocks, int& esc_p,
@@ -358,7 +372,7 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
   int p = sbin << hshift;
   if (BR && p == 0) p = 1;          // ordinal 1; entries below it are the zeros
   int c_end = 0;
-  return scan_select<KT, SHAPE>(p, sbase, k, cx, cy, T, a, om, rsp, blocks, c_end);
+  return scan_select<KT, SHAPE, OM_LDS>(p, sbase, k, cx, cy, T, a, om, rsp, blocks, c_end);
 }
 
 // Count change when the window centred at box (cx, cy) moves right by one
@@ -832,7 +846,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     const int kseed = GEN ? __builtin_amdgcn_readfirstlane(krow) : k0;
     int ep = 0, ec = 0;
     const long long cs0 = a.counters ? (long long)clock64() : 0;
-    int ms = seed_solve<KT, SHAPE, BR>(0 - a.dx_min, cy, Tv, hshift, kseed, a, om, I, hist, rsp,
+    int ms = seed_solve<KT, SHAPE, BR, !GS>(0 - a.dx_min, cy, Tv, hshift, kseed, a, om, I, hist, rsp,
                                        blocks, ep, ec);
     if (a.counters) seed_clk += (long long)clock64() - cs0;
     ++seeds;
@@ -852,7 +866,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
       const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow, hown);
       int c_end = 0;
-      ms = scan_core<SHAPE>(hp, cnt_new, kc, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
+      ms = scan_core<SHAPE, !GS>(hp, cnt_new, kc, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
                             om, rsp, blocks, pre_up, pre_dn, c_end);
       if (!BR || ms >= 0) {
         hp = ms;
@@ -915,7 +929,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       const int plL = __builtin_amdgcn_readlane(pl, L), clL = __builtin_amdgcn_readlane(cl, L);
       const int kL = GEN ? __builtin_amdgcn_readlane(kl, L) : k0;
       int c_end = 0;
-      const int mL = scan_select<KT, SHAPE>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
+      const int mL = scan_select<KT, SHAPE, !GS>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
                                             rsp, blocks, c_end);
       mnew = set_lane(mL, L, mnew);
       if (BR && mL < 0) {
