@@ -169,16 +169,17 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       // the load stays here instead of sinking into the continue path)
       const int ni = min(max(b + 64 + lane, 0), T - 1);
       const uint32_t nxt = OM_LDS ? lds_load_early(om, ni) : (uint32_t)om[ni];
-      // both tests evaluated (no branch): cur is always a loaded entry
-      const bool in = (b + lane < T) &
-                      member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
-      const uint64_t mask = wave_ballot(in);
+      // both tests evaluated (no branch; cur is always a loaded entry) and
+      // combined as lane masks
+      const uint64_t mask =
+          wave_ballot(b + lane < T) &
+          wave_ballot(member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp));
       const int pc = __popcll(mask);
       ++blocks;
       if (need < pc) {
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        const uint64_t hit = wave_ballot(in && below == need);
+        const uint64_t hit = mask & wave_ballot(below == need);
         return b + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
@@ -193,16 +194,16 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       const int ni = max(b - 128 + lane, 0);
       const uint32_t nxt = OM_LDS ? lds_load_early(om, ni) : (uint32_t)om[ni];
       const int v = b - 64 + lane;
-      const bool in = (v >= 0) & (v < T) &
-                      member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp);
-      const uint64_t mask = wave_ballot(in);
+      const uint64_t mask =
+          wave_ballot((v >= 0) & (v < T)) &
+          wave_ballot(member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp));
       const int pc = __popcll(mask);
       ++blocks;
       if (need <= pc) {
         const int idx = pc - need;
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        const uint64_t hit = wave_ballot(in && below == idx);
+        const uint64_t hit = mask & wave_ballot(below == idx);
         return b - 64 + (__ffsll((unsigned long long)hit) - 1);
       }
       need -= pc;
