@@ -281,17 +281,17 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
     q += up ? 8 : -8;
   }
   if (m >= 0) {
-    // the need-th member of the group (from the bottom going up, from the
-    // top going down)
-    int n = need, jsel = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int jj = up ? t : 7 - t;
-      if ((bits >> jj) & 1u) {
-        if (n == 0) jsel = jj;
-        --n;
-      }
-    }
+    // the need-th member of the group from the bottom going up, from the
+    // top going down (= member cnt - 1 - need from the bottom): the n-th set
+    // bit of the 8-bit mask by halving (nibble, pair, bit)
+    uint32_t x = bits;
+    int n = up ? need : __builtin_popcount(bits) - 1 - need;
+    int jsel = 0;
+    int cn = __builtin_popcount(x & 15u);
+    if (n >= cn) { n -= cn; jsel += 4; x >>= 4; }
+    cn = __builtin_popcount(x & 3u);
+    if (n >= cn) { n -= cn; jsel += 2; x >>= 2; }
+    if (n >= (int)(x & 1u)) jsel += 1;
     m = q + jsel;
   }
   groups += it;
