@@ -241,7 +241,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
   const bool up = c <= k;
   int need = up ? k - c : c - 1 - k;
   int q = up ? (p & ~7) : ((p - 1) & ~7);
-  int below = c;   // members below the frontier
+  const int need0 = need;   // members passed = need0 - need
   int m = -1, it = 0;
   uint32_t bits = 0;
   // first (partial) group: only ordinals in [p, T) (up) or [0, p) (down);
@@ -262,7 +262,6 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
       m = q;   // selection below
     } else {
       need -= cnt;
-      below += up ? cnt : -cnt;
       q += up ? 8 : -8;
     }
   }
@@ -277,7 +276,6 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
       break;
     }
     need -= cnt;
-    below += up ? cnt : -cnt;
     q += up ? 8 : -8;
   }
   if (m >= 0) {
@@ -299,7 +297,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
     p = up ? q : q + 8;
     if (p < 0) p = 0;
     if (p > T) p = T;
-    c = below;
+    c += up ? need0 - need : need - need0;   // members below the frontier
   }
   return m;
 }
