@@ -110,14 +110,18 @@ __device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, con
   if constexpr (SHAPE == SHAPE_DISC) {
     const s2v c = __builtin_bit_cast(s2v, cxy);
     const int negl = -a.limit - 1;
-    uint32_t acc = 0;
+    // all eight dot products first, then the sign bits shifted in (keeps
+    // each product's consumer away from it)
+    int r[8];
 #pragma unroll
-    for (int j = 7; j >= 0; --j) {
+    for (int j = 0; j < 8; ++j) {
       const uint32_t pk = __builtin_amdgcn_perm(0u, wv[j >> 1], (j & 1) ? 0x0c030c02u : 0x0c010c00u);
       const s2v d = __builtin_bit_cast(s2v, pk) - c;
-      const int r = dot2_sq_add(d, negl);
-      acc = __builtin_amdgcn_alignbit(acc, (uint32_t)r, 31u);
+      r[j] = dot2_sq_add(d, negl);
     }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) acc = __builtin_amdgcn_alignbit(acc, (uint32_t)r[j], 31u);
     return acc;
   } else {
     uint32_t bits = 0;
