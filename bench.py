@@ -1,7 +1,7 @@
 """Benchmark: exact median filter, 4096x4096 uint16 natural-like image, disc r=32, clamp.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--radius R] [--size S]
-                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks,stress]
+                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks,windows,stress]
                     [--weights PATH] [--copy-check]
 
 One step = one call of the plain filter over the whole image (every step of
@@ -23,6 +23,9 @@ Comparison legs in the same line:
              (one ordinal transform per tile) against three single-rank
              calls, and a per-pixel rank map running 0..100 % across the
              width against the median filter;
+  windows  - the headline image: medians over discs of radius 24/32/40 and
+             8/16/32 in one call each (windows of similar box size share one
+             ordinal transform per tile) against three plain calls;
   stress   - the slow input of the paper's limitations discussion (1024^2
              0/65535 checkerboard in a mid-grey frame, r=32), reported only.
 Each compares every output pixel with the plain filter's and a random sample
@@ -312,6 +315,55 @@ def leg_ranks(torch, mf, img, img_np, fp, ofp, reps, check_oracle, log):
     return res
 
 
+def leg_windows(torch, mf, img, img_np, reps, check_oracle, log):
+    """Headline image: medians over several disc radii in one call (the
+    library's grouping by box size) against one plain call per radius; radii
+    24/32/40 share one ordinal transform per tile, 8/16/32 are split into
+    passes (forced into one pass too, for comparison)."""
+    return {"similar": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
+                                     (24, 32, 40)),
+            "disparate": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
+                                       (8, 16, 32))}
+
+
+def _windows_case(torch, mf, img, img_np, reps, check_oracle, log, radii):
+    from oracle import footprints as OF
+    stream = torch.cuda.current_stream()
+    fps = [mf.Footprint.disc(r) for r in radii]
+    singles = [torch.empty_like(img) for _ in radii]
+    multi = [torch.empty_like(img) for _ in radii]
+
+    def run_singles():
+        for f, o in zip(fps, singles):
+            mf.median_filter(img, f, "clamp", out=o)
+
+    run_singles()
+    mf.window_filter(img, fps, "clamp", outs=multi)
+    t_single = float(np.median(_time_events(torch, run_singles, stream, reps)))
+    t_multi = float(np.median(_time_events(
+        torch, lambda: mf.window_filter(img, fps, "clamp", outs=multi), stream, reps)))
+    mism = sum(int((a != b).sum()) for a, b in zip(singles, multi))
+    mf.set_window_fusion(True)
+    try:
+        fused = [torch.empty_like(img) for _ in radii]
+        t_fused = float(np.median(_time_events(
+            torch, lambda: mf.window_filter(img, fps, "clamp", outs=fused), stream, reps)))
+    finally:
+        mf.set_window_fusion(False)
+    mism += sum(int((a != b).sum()) for a, b in zip(singles, fused))
+    res = {"radii": list(radii), "single_calls_ms": t_single, "one_call_ms": t_multi,
+           "speedup": t_single / t_multi, "all_in_one_pass_ms": t_fused,
+           "mismatches_multi_vs_single": mism}
+    if check_oracle:
+        got = [o.cpu().numpy() for o in multi]
+        res["oracle_mismatches"] = sum(_oracle_sample(img_np, OF.disc(r), g, 700, 200 + r)
+                                       for r, g in zip(radii, got))
+        res["oracle_checked_px"] = 700 * len(radii)
+    log(f"# windows {list(radii)}: {len(radii)} plain calls {t_single:.2f} ms, "
+        f"one call {t_multi:.2f} ms, all in one pass {t_fused:.2f} ms")
+    return res
+
+
 def leg_stress(torch, mf, reps, check_oracle, log):
     """1024x1024 uint16 0/65535 checkerboard inside a mid-grey frame, disc
     r=32: the input the paper's limitations discussion describes as slow
@@ -351,7 +403,7 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="plain,batched,learned,ranks,stress")
+    ap.add_argument("--legs", default="plain,batched,learned,ranks,windows,stress")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
                                                       "bracket_net.npz"))
     ap.add_argument("--copy-check", action="store_true")
@@ -444,6 +496,8 @@ def main():
         ranks = leg_ranks(torch, mf, img, img_np, fp, OF.disc(r), 5, not args.no_cpu, log)
     else:
         ranks = None
+    windows = (leg_windows(torch, mf, img, img_np, 5, not args.no_cpu, log)
+               if "windows" in legs else None)
     stress = leg_stress(torch, mf, 5, not args.no_cpu, log) if "stress" in legs else None
 
     cpu = None
@@ -504,6 +558,7 @@ def main():
         "batched": batched,
         "learned": learned,
         "ranks": ranks,
+        "windows": windows,
         "stress": stress,
     }
     print(json.dumps(line))

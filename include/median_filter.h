@@ -160,6 +160,54 @@ int median_filter_rank_map(const void* img, int w, int h, size_t stride_bytes, i
                            size_t rank_map_stride_bytes, void* out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Several windows from one ordinal transform (paper, Discussion
+ * "Multi-Parameter Filtering": one ordinal transform can serve filters of
+ * several radii, as long as each tile's box holds all their windows).
+ *
+ * median_filter_windows writes `nouts` planes (1..MF_MAX_RANK_OUTPUTS) of
+ * img, each with its own footprint: plane q (outs[q].out, same shape and
+ * stride as img) holds at pixel (x, y) the element of zero-based rank
+ *   rank_map[y * (rank_map_stride_bytes / 4) + x], clamped to [0, N_q - 1],
+ *   where outs[q].rank_map is not NULL (as in mf_rank_output), else
+ *   outs[q].rank (must be < N_q, else MF_ERR_INVALID_ARG; a negative rank
+ *   selects the median (N_q - 1) / 2)
+ * of the window outs[q].footprint (N_q taps) centred there.  Every
+ * footprint must be non-NULL (MF_ERR_INVALID_ARG).
+ *
+ * The windows are grouped into passes: in decreasing order of the box
+ * their own single-window plan loads (T_q pixels, for tiles of P_q), window
+ * q joins the current pass, whose first window's box has T_0 pixels, while
+ * (T_q / P_q) * N_q >= 0.25 * (T_0 - T_q), else it starts a new pass (a
+ * small window in a much larger box walks over the extra pixels in every
+ * omnigram scan, which can cost more than the shared sort saves; similar
+ * windows share one pass).  A pass of one window is a median_filter_rank /
+ * median_filter_rank_map call.  A pass of several loads and sorts each
+ * tile's box (that of the smallest offset rectangle holding the pass's
+ * windows) once and runs its bands once per plane with that plane's
+ * window; if all of them are discs the disc membership test is used,
+ * otherwise the span test.  Passes are queued in order on `stream`.  The
+ * planes equal, bit for bit, separate median_filter_rank /
+ * median_filter_rank_map calls.  Aliasing rules, errors and stream
+ * semantics as median_filter_ranks.
+ *
+ * mf_set_window_fusion(1) makes every later call use one pass for all its
+ * windows (measurement and tests); 0 restores the grouping.  Process-wide;
+ * returns MF_OK.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  void* out;                        /* device plane */
+  const mf_footprint* footprint;    /* this plane's window */
+  int rank;                         /* used where rank_map is NULL; < 0: median */
+  const int* rank_map;              /* device int32 plane or NULL */
+  size_t rank_map_stride_bytes;     /* row stride of rank_map */
+} mf_window_output;
+
+int median_filter_windows(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          int boundary, const mf_window_output* outs, int nouts,
+                          hipStream_t stream);
+int mf_set_window_fusion(int all);
+
+/* ------------------------------------------------------------------------
  * Batched filtering (not in the paper): many images of any sizes, dtypes
  * and footprints in one persistent launch.
  *

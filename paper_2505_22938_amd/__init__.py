@@ -56,6 +56,8 @@ def lib():
         "median_filter_rank": ([P, I, I, SZ, I, P, I, I, P, P], I),
         "median_filter_ranks": ([P, I, I, SZ, I, P, I, P, I, P], I),
         "median_filter_rank_map": ([P, I, I, SZ, I, P, I, P, SZ, P, P], I),
+        "median_filter_windows": ([P, I, I, SZ, I, I, P, I, P], I),
+        "mf_set_window_fusion": ([I], I),
         "mf_set_tile_override": ([I, I], I),
         "mf_query_plan": ([I, I, I, P, IP, IP, IP, IP, IP], I),
         "mf_work_counters": ([I, P], I),
@@ -305,6 +307,58 @@ def rank_map_filter(img, fp: Footprint, rank_map, boundary: str = "clamp", out=N
                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     _check("median_filter_rank_map", rc)
     return out
+
+
+class _WindowOutput(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("footprint", ctypes.c_void_p), ("rank", ctypes.c_int),
+                ("rank_map", ctypes.c_void_p), ("rank_map_stride_bytes", ctypes.c_size_t)]
+
+
+def window_filter(img, windows, boundary: str = "clamp", outs=None, stream=None):
+    """Planes of `img` over several windows from one ordinal transform per tile.
+
+    `windows` lists one entry per output plane: a Footprint (its median), or
+    a (Footprint, rank) pair where rank is an int (zero-based, < N of that
+    footprint; negative: the median) or a (h, w) int32 device tensor of
+    per-pixel ranks (clamped to [0, N - 1]).  Returns the list of output
+    tensors (`outs`, if given, must match `img` in shape, dtype and strides).
+    Each plane equals the single-window filter of the same footprint and rank.
+    Windows whose boxes are of similar size share one ordinal transform per
+    tile; the others run in passes of their own (set_window_fusion)."""
+    import torch
+    code, es, w, h, stride_bytes = _plane_args(img)
+    windows = [wi if isinstance(wi, tuple) else (wi, -1) for wi in windows]
+    if not 1 <= len(windows) <= MAX_RANK_OUTPUTS:
+        raise ValueError(f"1..{MAX_RANK_OUTPUTS} planes per call")
+    if outs is None:
+        outs = [torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+                for _ in windows]
+    if len(outs) != len(windows):
+        raise ValueError("one output per window")
+    arr = (_WindowOutput * len(windows))()
+    for q, ((fp, rk), o) in enumerate(zip(windows, outs)):
+        if o.shape != img.shape or o.dtype != img.dtype or o.stride() != img.stride():
+            raise ValueError("outputs must match img in shape, dtype and strides")
+        if isinstance(rk, int):
+            arr[q] = _WindowOutput(o.data_ptr(), fp.handle, int(rk), None, 0)
+        else:
+            if rk.dtype != torch.int32 or tuple(rk.shape) != (h, w) or not rk.is_cuda:
+                raise ValueError("a rank map is an int32 (h, w) device tensor")
+            if rk.stride(1) != 1:
+                raise ValueError("rank map rows must be contiguous")
+            arr[q] = _WindowOutput(o.data_ptr(), fp.handle, 0, rk.data_ptr(),
+                                   rk.stride(0) * 4 if h > 1 else w * 4)
+    rc = lib().median_filter_windows(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes, code,
+                                     BOUNDARY[boundary], ctypes.cast(arr, ctypes.c_void_p),
+                                     len(windows), _stream_ptr(stream))
+    _check("median_filter_windows", rc)
+    return outs
+
+
+def set_window_fusion(all_in_one_pass: bool):
+    """window_filter: one pass for all windows (True) or the default grouping
+    by box size (False).  Process-wide."""
+    lib().mf_set_window_fusion(1 if all_in_one_pass else 0)
 
 
 def set_tile_override(tile_w: int = 0, tile_h: int = 0):

@@ -43,6 +43,15 @@ enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };
 // value to the plain kernels and stored in the batched descriptor table.
 constexpr int kMaxRankOutputs = MF_MAX_RANK_OUTPUTS;   // planes of one general-rank call
 
+// Window of one output plane when the planes of a general-rank call use
+// different footprints (all inside the plan's box): its device span table
+// (rows then columns, as ImageDesc::spans), geometry, disc limit and the
+// largest valid rank (taps - 1).
+struct PlaneFp {
+  const short2* spans;
+  int dx_min, dy_min, nrows, ncols, limit, rank_hi;
+};
+
 struct ImageDesc {
   const void* img;
   void* out;
@@ -81,6 +90,10 @@ struct ImageDesc {
   const int* rmaps[kMaxRankOutputs];
   long long rmap_strides[kMaxRankOutputs];  // elements
   int ranks[kMaxRankOutputs];
+  // multi_fp = 1: plane q uses the window pfp[q] instead of the plan's
+  // (whose box, tables and kernel shape cover all of them)
+  int multi_fp;
+  PlaneFp pfp[kMaxRankOutputs];
 };
 
 struct DeviceInfo {
@@ -134,6 +147,13 @@ unsigned long long* work_counters_ptr();
 using PlainKernelFn = void (*)(ImageDesc);
 int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream);
 PlainKernelFn pick_general_kernel(const ImageDesc& d);
+// median_filter_windows: one pass for all windows (set by
+// mf_set_window_fusion) instead of grouping them by box size.
+bool window_fusion_all();
+void set_window_fusion_all(int all);
+int launch_window_pass(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                       int boundary, const mf_window_output* outs, const int* idx, int n,
+                       int dev, const DeviceInfo& di, hipStream_t stream);
 
 // Tile-shape override (measurement): 0 = off.
 void get_override(int* tw, int* th);

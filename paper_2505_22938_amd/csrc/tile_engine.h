@@ -81,6 +81,14 @@ __device__ __forceinline__ int dot2_sq_add(s2v d, int c) {
   return r;
 }
 
+// Footprint geometry seen by the scans, walks and seed solves: the disc's
+// squared-radius limit, the first row offset and the row count (row spans
+// are in the LDS table rsp, index dy - dy_min).  One per output plane when
+// planes use different windows.
+struct Fp {
+  int limit, dy_min, nrows;
+};
+
 // Window membership of an omnigram entry (paper, Eq. 2/3).  `w` holds the
 // entry's box location in its low 16 bits (x: bits 0-7, y: bits 8-15);
 // `cxy` is the window centre packed as x | y << 16.  The offset is formed
@@ -103,13 +111,13 @@ __device__ __forceinline__ bool member_packed(uint32_t w, uint32_t cxy, int limi
 // Membership of the eight omnigram entries in g (two per word), bit j for
 // entry j.  Disc: per entry one byte permute, one packed subtract and one
 // dot product whose sign bit is shifted into the mask (v_alignbit).
-template <int SHAPE, typename D>
-__device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, const D& a,
+template <int SHAPE>
+__device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, const Fp& f,
                                                const short2* rsp) {
   const uint32_t wv[4] = {g.x, g.y, g.z, g.w};
   if constexpr (SHAPE == SHAPE_DISC) {
     const s2v c = __builtin_bit_cast(s2v, cxy);
-    const int negl = -a.limit - 1;
+    const int negl = -f.limit - 1;
     // all eight dot products first, then the sign bits shifted in (keeps
     // each product's consumer away from it)
     int r[8];
@@ -128,7 +136,7 @@ __device__ __forceinline__ uint32_t group_mask(const uint4& g, uint32_t cxy, con
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const uint32_t e = (j & 1) ? (wv[j >> 1] >> 16) : wv[j >> 1];
-      bits |= (uint32_t)member_packed<SHAPE>(e, cxy, a.limit, a.dy_min, a.nrows, rsp) << j;
+      bits |= (uint32_t)member_packed<SHAPE>(e, cxy, f.limit, f.dy_min, f.nrows, rsp) << j;
     }
     return bits;
   }
@@ -159,7 +167,7 @@ __device__ __forceinline__ uint32_t lds_load_early(const uint16_t* base, int i) 
 // up, below ordinal 0 going down).
 template <int SHAPE, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int T,
-                                         const D& a, const uint16_t* om,
+                                         const D& a, const Fp& f, const uint16_t* om,
                                          const short2* rsp, int& blocks, uint32_t pre_up,
                                          uint32_t pre_dn, int& c_end) {
   const int lane = threadIdx.x & 63;
@@ -177,7 +185,7 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       // combined as lane masks
       const uint64_t mask =
           wave_ballot(b + lane < T) &
-          wave_ballot(member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp));
+          wave_ballot(member_packed<SHAPE>(cur, cxy, f.limit, f.dy_min, f.nrows, rsp));
       const int pc = __popcll(mask);
       ++blocks;
       if (need < pc) {
@@ -200,7 +208,7 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
       const int v = b - 64 + lane;
       const uint64_t mask =
           wave_ballot((v >= 0) & (v < T)) &
-          wave_ballot(member_packed<SHAPE>(cur, cxy, a.limit, a.dy_min, a.nrows, rsp));
+          wave_ballot(member_packed<SHAPE>(cur, cxy, f.limit, f.dy_min, f.nrows, rsp));
       const int pc = __popcll(mask);
       ++blocks;
       if (need <= pc) {
@@ -220,13 +228,13 @@ __device__ __forceinline__ int scan_core(int p, int c, int k, uint32_t cxy, int 
 
 template <int KT, int SHAPE, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, int T,
-                                           const D& a, const uint16_t* om,
+                                           const D& a, const Fp& f, const uint16_t* om,
                                            const short2* rsp, int& blocks, int& c_end) {
   const int lane = threadIdx.x & 63;
   const uint32_t cxy = (uint32_t)cx | ((uint32_t)cy << 16);
   const bool up = c <= k;
   const uint32_t pre = up ? om[min(max(p + lane, 0), T - 1)] : om[max(p - 64 + lane, 0)];
-  return scan_core<SHAPE, OM_LDS>(p, c, k, cxy, T, a, om, rsp, blocks, pre, pre, c_end);
+  return scan_core<SHAPE, OM_LDS>(p, c, k, cxy, T, a, f, om, rsp, blocks, pre, pre, c_end);
 }
 
 // Lane-parallel rank selection: every lane refines its own window.  Same
@@ -238,9 +246,9 @@ __device__ __forceinline__ int scan_select(int p, int c, int k, int cx, int cy, 
 // entries located outside the box, so only the first group needs a range
 // test.  After `budget` groups an unfinished lane returns -1 with (p, c) set
 // to its frontier, for a wave-cooperative finish.
-template <int SHAPE, typename D>
+template <int SHAPE>
 __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, int budget, int T,
-                                           const D& a, const uint16_t* om,
+                                           const Fp& f, const uint16_t* om,
                                            const short2* rsp, int& groups) {
   const bool up = c <= k;
   int need = up ? k - c : c - 1 - k;
@@ -259,7 +267,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
     } else {
       range = (1u << (p - q)) - 1u;
     }
-    bits = group_mask<SHAPE>(g, cxy, a, rsp) & range;
+    bits = group_mask<SHAPE>(g, cxy, f, rsp) & range;
     const int cnt = __builtin_popcount(bits);
     ++it;
     if (need < cnt) {
@@ -272,7 +280,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
   // full groups: count members only
   while (m < 0 && (up ? q < T : q >= 0) && it < budget) {
     const uint4 g = *reinterpret_cast<const uint4*>(om + q);
-    bits = group_mask<SHAPE>(g, cxy, a, rsp);
+    bits = group_mask<SHAPE>(g, cxy, f, rsp);
     const int cnt = __builtin_popcount(bits);
     ++it;
     if (need < cnt) {
@@ -315,7 +323,7 @@ __device__ __forceinline__ int lane_select(int& p, int& c, int k, uint32_t cxy, 
 // window members below that ordinal, so sliding can go on from there.
 template <int KT, int SHAPE, bool BR, bool OM_LDS = true, typename D>
 __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int k, const D& a,
-                                          const uint16_t* om, const uint16_t* I, uint32_t* hist,
+                                          const Fp& f, const uint16_t* om, const uint16_t* I, uint32_t* hist,
                                           const short2* rsp, int& blocks, int& esc_p,
                                           int& esc_c) {
   const int lane = threadIdx.x & 63;
@@ -327,9 +335,9 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
   hist[lane * 2] = 0;
   hist[lane * 2 + 1] = 0;
   wave_lds_sync();
-  for (int i = lane; i < a.nrows; i += 64) {
+  for (int i = lane; i < f.nrows; i += 64) {
     const short2 s = rsp[i];
-    const int row = (cy + a.dy_min + i) * a.pitch + cx;
+    const int row = (cy + f.dy_min + i) * a.pitch + cx;
     for (int x = s.x; x <= s.y; ++x) {
       const uint32_t iv = I[row + x];
       if (BR) {
@@ -375,7 +383,7 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
   int p = sbin << hshift;
   if (BR && p == 0) p = 1;          // ordinal 1; entries below it are the zeros
   int c_end = 0;
-  return scan_select<KT, SHAPE, OM_LDS>(p, sbase, k, cx, cy, T, a, om, rsp, blocks, c_end);
+  return scan_select<KT, SHAPE, OM_LDS>(p, sbase, k, cx, cy, T, a, f, om, rsp, blocks, c_end);
 }
 
 // Count change when the window centred at box (cx, cy) moves right by one
@@ -383,7 +391,7 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
 // further rounds of 128 rows for taller windows); hrow[i] = (entering
 // offset, leaving offset) of row i.
 template <typename D>
-__device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a,
+__device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a, const Fp& f,
                                            const uint16_t* I, const int2* hrow,
                                            const int4& own) {
   const int lane = threadIdx.x & 63;
@@ -394,15 +402,15 @@ __device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a,
               __popcll(wave_ballot(I[base + own.y] < p)) +
               __popcll(wave_ballot(I[base + own.z] < p)) -
               __popcll(wave_ballot(I[base + own.w] < p));
-  for (int i0 = 128; i0 < a.nrows; i0 += 128) {
+  for (int i0 = 128; i0 < f.nrows; i0 += 128) {
     const int i1 = i0 + lane, i2 = i0 + 64 + lane;
     bool e1 = false, l1 = false, e2 = false, l2 = false;
-    if (i1 < a.nrows) {
+    if (i1 < f.nrows) {
       const int2 o = hrow[i1];
       e1 = I[base + o.x] < p;
       l1 = I[base + o.y] < p;
     }
-    if (i2 < a.nrows) {
+    if (i2 < f.nrows) {
       const int2 o = hrow[i2];
       e2 = I[base + o.x] < p;
       l2 = I[base + o.y] < p;
@@ -442,14 +450,15 @@ __device__ __forceinline__ void store_out(const D& a, void* out, int gx, int gy,
 
 // Rank of output pixel (gx, gy) in plane q of the general form: the plane's
 // rank map entry clamped to [0, N) where the plane has a map and the pixel
-// is inside the image, else the plane's constant rank k0.
+// is inside the image, else the plane's constant rank k0.  N is the plane's
+// window size (its own window under multi_fp).
 template <bool GEN, typename D>
 __device__ __forceinline__ int rank_at(const D& a, int q, int k0, int gx, int gy, bool inside) {
   if (!GEN) return k0;
   const int* rm = a.rmaps[q];
   if (!rm || !inside) return k0;
   const int v = rm[(long long)gy * a.rmap_strides[q] + gx];
-  return min(max(v, 0), a.rank_hi);
+  return min(max(v, 0), a.multi_fp ? a.pfp[q].rank_hi : a.rank_hi);
 }
 
 // Bracketed tiles: append the flagged output pixels of the wave (index
@@ -542,18 +551,34 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   int mlo = 0;       // smallest ordinal a member may have
 
   // footprint tables: row spans, per-row horizontal offsets, per-column
-  // vertical offsets (down: entering, leaving; up: entering, leaving)
-  for (int i = t; i < a.nrows; i += kThreads) {
-    const short2 s = a.spans[i];
-    rsp[i] = s;
-    const int dy = a.dy_min + i;
-    hrow[i] = make_int2(dy * a.pitch + s.y + 1, dy * a.pitch + s.x);
-  }
-  for (int j = t; j < a.ncols; j += kThreads) {
-    const short2 s = a.spans[a.nrows + j];
-    const int dx = a.dx_min + j;
-    vtab[j] = make_int4((s.y + 1) * a.pitch + dx, s.x * a.pitch + dx,
-                        (s.x - 1) * a.pitch + dx, s.y * a.pitch + dx);
+  // vertical offsets (down: entering, leaving; up: entering, leaving), all
+  // relative to the window centre.  Planes with windows of their own
+  // (multi_fp) rebuild them per plane inside the box of the plan, whose
+  // offsets (a.dx_min, a.dy_min) still place the centres.
+  auto build_tables = [&](const short2* spans, int nrows, int ncols, int dx_min, int dy_min) {
+    for (int i = t; i < nrows; i += kThreads) {
+      const short2 s = spans[i];
+      rsp[i] = s;
+      const int dy = dy_min + i;
+      hrow[i] = make_int2(dy * a.pitch + s.y + 1, dy * a.pitch + s.x);
+    }
+    for (int j = t; j < ncols; j += kThreads) {
+      const short2 s = spans[nrows + j];
+      const int dx = dx_min + j;
+      vtab[j] = make_int4((s.y + 1) * a.pitch + dx, s.x * a.pitch + dx,
+                          (s.x - 1) * a.pitch + dx, s.y * a.pitch + dx);
+    }
+  };
+  const bool mfp = GEN && a.multi_fp;
+  Fp f{a.limit, a.dy_min, a.nrows};
+  int fcols = a.ncols;
+  if (mfp) {
+    const auto& p0 = a.pfp[0];
+    f = Fp{p0.limit, p0.dy_min, p0.nrows};
+    fcols = p0.ncols;
+    build_tables(p0.spans, p0.nrows, p0.ncols, p0.dx_min, p0.dy_min);
+  } else {
+    build_tables(a.spans, a.nrows, a.ncols, a.dx_min, a.dy_min);
   }
 
   uint64_t below_bits = 0, above_bits = 0;   // BR: classes of this thread's chunks
@@ -814,17 +839,33 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   const int row0 = band * R;                 // first output row of this lane's band
   const int cxl = col - a.dx_min;            // lane's window centre, box coords
   const int cols_in = min(tw, a.w - tx0);
-  int4 hown = make_int4(0, 0, 0, 0);   // this lane's rows of hrow (lane, lane + 64)
-  if (lane < a.nrows) {
-    hown.x = hrow[lane].x;
-    hown.y = hrow[lane].y;
-  }
-  if (lane + 64 < a.nrows) {
-    hown.z = hrow[lane + 64].x;
-    hown.w = hrow[lane + 64].y;
-  }
+  // this lane's rows of hrow (lane, lane + 64); rows beyond the footprint
+  // read one entry twice and cancel
+  auto own_rows = [&]() {
+    int4 o = make_int4(0, 0, 0, 0);
+    if (lane < f.nrows) {
+      o.x = hrow[lane].x;
+      o.y = hrow[lane].y;
+    }
+    if (lane + 64 < f.nrows) {
+      o.z = hrow[lane + 64].x;
+      o.w = hrow[lane + 64].y;
+    }
+    return o;
+  };
+  int4 hown = own_rows();
   const int nq = GEN ? a.nq : 1;
   for (int q = 0; q < nq; ++q) {
+  if (mfp && q > 0) {
+    // this plane's window: every wave is done with the previous tables
+    const auto& pq = a.pfp[q];
+    __syncthreads();
+    f = Fp{pq.limit, pq.dy_min, pq.nrows};
+    fcols = pq.ncols;
+    build_tables(pq.spans, pq.nrows, pq.ncols, pq.dx_min, pq.dy_min);
+    __syncthreads();
+    hown = own_rows();
+  }
   void* const outq = GEN ? a.outs[q] : a.out;
   const int k0 = GEN ? a.ranks[q] : a.rank;
   const long long clkq = GEN && a.counters ? (long long)clock64() : clk1;
@@ -849,7 +890,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     const int kseed = GEN ? __builtin_amdgcn_readfirstlane(krow) : k0;
     int ep = 0, ec = 0;
     const long long cs0 = a.counters ? (long long)clock64() : 0;
-    int ms = seed_solve<KT, SHAPE, BR, !GS>(0 - a.dx_min, cy, Tv, hshift, kseed, a, om, I, hist, rsp,
+    int ms = seed_solve<KT, SHAPE, BR, !GS>(0 - a.dx_min, cy, Tv, hshift, kseed, a, f, om, I, hist, rsp,
                                        blocks, ep, ec);
     if (a.counters) seed_clk += (long long)clock64() - cs0;
     ++seeds;
@@ -867,10 +908,10 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       const int cxp = c - 1 - a.dx_min;
       const uint32_t pre_up = om[min(hp + lane, Tv - 1)];
       const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
-      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, I, hrow, hown);
+      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, f, I, hrow, hown);
       int c_end = 0;
       ms = scan_core<SHAPE, !GS>(hp, cnt_new, kc, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
-                            om, rsp, blocks, pre_up, pre_dn, c_end);
+                            f, om, rsp, blocks, pre_up, pre_dn, c_end);
       if (!BR || ms >= 0) {
         hp = ms;
         hc = kc;
@@ -908,7 +949,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     int delta = 0;
     if (lane_active) {
 #pragma unroll 4
-      for (int j = 0; j < a.ncols; ++j) {
+      for (int j = 0; j < fcols; ++j) {
         const int4 o = vtab[j];
         delta += (int)(I[lbase + o.x] < vp) - (int)(I[lbase + o.y] < vp);
       }
@@ -917,7 +958,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     int mnew = m, esc = 0;
     const uint32_t cxy = (uint32_t)cxl | ((uint32_t)(row0 + r - a.dy_min) << 16);
     if (lane_active) {
-      mnew = lane_select<SHAPE>(pl, cl, kl, cxy, kLaneBudget, Tv, a, om, rsp, groups);
+      mnew = lane_select<SHAPE>(pl, cl, kl, cxy, kLaneBudget, Tv, f, om, rsp, groups);
       if (BR && mnew < 0 && (pl <= 0 || pl >= Tv)) {
         // walked off an end of the bracket: a miss
         esc = 1;
@@ -932,8 +973,8 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       const int plL = __builtin_amdgcn_readlane(pl, L), clL = __builtin_amdgcn_readlane(cl, L);
       const int kL = GEN ? __builtin_amdgcn_readlane(kl, L) : k0;
       int c_end = 0;
-      const int mL = scan_select<KT, SHAPE, !GS>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, om,
-                                            rsp, blocks, c_end);
+      const int mL = scan_select<KT, SHAPE, !GS>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, f,
+                                            om, rsp, blocks, c_end);
       mnew = set_lane(mL, L, mnew);
       if (BR && mL < 0) {
         pl = set_lane(clL <= kL ? Tv : 1, L, pl);

@@ -197,3 +197,30 @@ def test_rank_outputs_argument_validation_is_host_side():
     assert call([(o1, 6, None, 0)], w=0) == 0                        # empty image: no work
     assert L.median_filter_rank_map(P(img), 8, 8, 8, 0, fp.handle, 0, None, 32, P(o1),
                                     None) == -1                      # null rank map
+
+
+def test_window_outputs_argument_validation_is_host_side():
+    """median_filter_windows rejects bad arguments before any GPU work."""
+    L = mf.lib()
+    small, big = mf.Footprint.disc(2), mf.Footprint.disc(4)   # 13 and 49 taps
+    P = ctypes.c_void_p
+    img, o1, o2, rm = 4096, 1 << 20, 1 << 21, 1 << 22
+
+    def call(specs, n=None, w=8, h=8):
+        arr = (mf._WindowOutput * max(1, len(specs)))()
+        for i, (out, fp, rank, rmap, stride) in enumerate(specs):
+            arr[i] = mf._WindowOutput(out, fp.handle if fp else None, rank, rmap, stride)
+        return L.median_filter_windows(P(img), w, h, 8, 0, 0, ctypes.cast(arr, ctypes.c_void_p),
+                                       len(specs) if n is None else n, None)
+
+    assert call([(o1, small, 6, None, 0)], n=0) == -1                 # no planes
+    assert call([(o1, small, 6, None, 0)] * 9) == -1                  # more than 8
+    assert call([(o1, small, 13, None, 0)]) == -1                     # rank >= N of its window
+    assert call([(o1, big, 13, None, 0), (o2, small, 13, None, 0)]) == -1
+    assert call([(o1, None, 0, None, 0)]) == -1                       # null footprint
+    assert call([(o1, small, 0, rm, 28)]) == -1                       # map stride < 4 w
+    assert call([(o1, small, 0, None, 0), (o1, big, 0, None, 0)]) == -2   # one buffer twice
+    assert call([(img + 8, big, 0, None, 0)]) == -2                   # output overlaps image
+    assert call([(o1, small, 0, o2, 32), (o2, big, 0, None, 0)]) == -2    # map over an output
+    assert call([(None, big, 0, None, 0)]) == -1                      # null output
+    assert call([(o1, small, -1, None, 0), (o2, big, 48, None, 0)], w=0) == 0   # empty image
