@@ -487,10 +487,6 @@ def main():
         del src, dst
 
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    batched = (leg_batched(torch, mf, 5, not args.no_cpu, log, autotune=not args.no_autotune)
-               if "batched" in legs else None)
-    learned = (leg_learned(torch, mf, args.weights, 5, not args.no_cpu, log)
-               if "learned" in legs else None)
     if "ranks" in legs:
         from oracle import footprints as OF
         ranks = leg_ranks(torch, mf, img, img_np, fp, OF.disc(r), 5, not args.no_cpu, log)
@@ -498,7 +494,13 @@ def main():
         ranks = None
     windows = (leg_windows(torch, mf, img, img_np, 5, not args.no_cpu, log)
                if "windows" in legs else None)
+    learned = (leg_learned(torch, mf, args.weights, 5, not args.no_cpu, log)
+               if "learned" in legs else None)
     stress = leg_stress(torch, mf, 5, not args.no_cpu, log) if "stress" in legs else None
+    # last: the batched leg records autotuned tile shapes, which every later
+    # plan in this process would use instead of the default ones
+    batched = (leg_batched(torch, mf, 5, not args.no_cpu, log, autotune=not args.no_autotune)
+               if "batched" in legs else None)
 
     cpu = None
     mismatches = None
