@@ -185,7 +185,9 @@ int median_filter_rank_map(const void* img, int w, int h, size_t stride_bytes, i
  * tile's box (that of the smallest offset rectangle holding the pass's
  * windows) once and runs its bands once per plane with that plane's
  * window; if all of them are discs the disc membership test is used,
- * otherwise the span test.  Passes are queued in order on `stream`.  The
+ * otherwise the span test.  Windows whose common rectangle exceeds the
+ * largest box (off-centre shapes on opposite sides) run one pass each.
+ * Passes are queued in order on `stream`.  The
  * planes equal, bit for bit, separate median_filter_rank /
  * median_filter_rank_map calls.  Aliasing rules, errors and stream
  * semantics as median_filter_ranks.

@@ -116,7 +116,16 @@ int launch_window_pass(const void* img, int w, int h, size_t stride_bytes, int d
   }
   int rc;
   ImageDesc a{};
-  if ((rc = choose_plan(dtype, &hull, di.lds_max, 33, &a, w, h, di.cus))) return rc;
+  if ((rc = choose_plan(dtype, &hull, di.lds_max, 33, &a, w, h, di.cus))) {
+    if (rc != MF_ERR_UNSUPPORTED) return rc;
+    // windows that each fit but whose rectangle does not (off-centre
+    // shapes on opposite sides): one pass per window
+    for (int i = 0; i < n; ++i)
+      if ((rc = launch_window_pass(img, w, h, stride_bytes, dtype, boundary, outs, idx + i, 1,
+                                   dev, di, stream)))
+        return rc;
+    return MF_OK;
+  }
   const void* table0 = nullptr;
   if ((rc = footprint_device_table(outs[idx[0]].footprint, dev, &table0))) return rc;
   bind_image(&a, img, w, h, stride_bytes, dtype, &hull, boundary, 0, table0);

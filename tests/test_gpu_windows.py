@@ -128,6 +128,21 @@ def test_odd_tile_shapes(mf, oracle_mod, fusion, tile):
         assert same(o.cpu().numpy(), oracle_mod.filter(img, OF.disc(r), "clamp")), (tile, r)
 
 
+def test_off_centre_windows_beyond_one_box(mf, oracle_mod, fusion):
+    """Two 201-pixel-wide bars on opposite sides of the centre: each fits a
+    box, their common rectangle (401 wide) does not, so each gets its own
+    pass even when one pass is requested."""
+    right = [(0.0, -3.0), (200.0, -3.0), (200.0, 3.0), (0.0, 3.0)]
+    left = [(-200.0, -3.0), (0.0, -3.0), (0.0, 3.0), (-200.0, 3.0)]
+    w, h = 90, 23
+    img = image("u8", w, h, 46)
+    outs = mf.window_filter(dev(img), [mf.Footprint.polygon(right), mf.Footprint.polygon(left)],
+                            "mirror")
+    torch.cuda.synchronize()
+    for verts, o in zip((right, left), outs):
+        assert same(o.cpu().numpy(), oracle_mod.filter(img, OF.polygon(verts), "mirror"))
+
+
 def test_errors_and_empty(mf, fusion):
     d = dev(image("u8", 40, 30, 45))
     fp = mf.Footprint.disc(2)
