@@ -102,6 +102,21 @@ def test_mixed_shapes_ranks_and_maps(mf, oracle_mod, fusion, dt):
         assert same(o.cpu().numpy(), exp), (dt, q)
 
 
+def test_rank_map_clamped_to_its_own_window(mf, oracle_mod, fusion):
+    """A rank-map plane on a small window beside a larger one: its entries
+    beyond its own N are clamped to its own maximum, not the larger
+    window's."""
+    w, h = 77, 53
+    img = image("u16", w, h, 47)
+    small = OF.disc(4)
+    rm = workloads.random_ranks(w, h, len(small), 13)
+    outs = mf.window_filter(dev(img), [mf.Footprint.disc(12), (mf.Footprint.disc(4), dev(rm))],
+                            "clamp")
+    torch.cuda.synchronize()
+    assert same(outs[0].cpu().numpy(), oracle_mod.filter(img, OF.disc(12), "clamp"))
+    assert same(outs[1].cpu().numpy(), oracle_mod.filter(img, small, "clamp", rank_map=rm))
+
+
 @pytest.mark.parametrize("dt,radii", [("u16", (64, 8)), ("u8", (1, 60)), ("f32", (40, 2, 20))])
 def test_large_boxes(mf, oracle_mod, fusion, dt, radii):
     """Boxes taken by the global-scratch and largest register plans, with a
