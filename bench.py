@@ -25,7 +25,9 @@ Comparison legs in the same line:
              width against the median filter;
   windows  - the headline image: medians over discs of radius 24/32/40 and
              8/16/32 in one call each (windows of similar box size share one
-             ordinal transform per tile) against three plain calls;
+             ordinal transform per tile), and one 3840x2160 float32
+             log-normal plane with its disc r=48, ellipse and hexagon windows
+             (mirror), each against one plain call per window;
   stress   - the slow input of the paper's limitations discussion (1024^2
              0/65535 checkerboard in a mid-grey frame, r=32), reported only.
 Each compares every output pixel with the plain filter's and a random sample
@@ -320,46 +322,71 @@ def leg_windows(torch, mf, img, img_np, reps, check_oracle, log):
     library's grouping by box size) against one plain call per radius; radii
     24/32/40 share one ordinal transform per tile, 8/16/32 are split into
     passes (forced into one pass too, for comparison)."""
-    return {"similar": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
-                                     (24, 32, 40)),
-            "disparate": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
-                                       (8, 16, 32))}
-
-
-def _windows_case(torch, mf, img, img_np, reps, check_oracle, log, radii):
+    import workloads
     from oracle import footprints as OF
+    discs = lambda radii: ([mf.Footprint.disc(r) for r in radii],   # noqa: E731
+                           [OF.disc(r) for r in radii], [f"disc r={r}" for r in radii])
+    res = {"similar": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
+                                    *discs((24, 32, 40)), "clamp"),
+           "disparate": _windows_case(torch, mf, img, img_np, reps, check_oracle, log,
+                                      *discs((8, 16, 32)), "clamp")}
+    # the float workload: one 3840x2160 log-normal plane, its three windows
+    f32 = np.ascontiguousarray(workloads.lognormal_f32(3840, 2160, planes=1, seed=2)[0])
+    res["f32_three_shapes"] = _windows_case(
+        torch, mf, torch.from_numpy(f32).cuda(), f32, reps, check_oracle, log,
+        [mf.Footprint.disc(48), mf.Footprint.ellipse(60, 20, 30),
+         mf.Footprint.regular_polygon(6, 40)],
+        [OF.disc(48), OF.ellipse(60, 20, 30), OF.regular_polygon(6, 40)],
+        ["disc r=48", "ellipse 60x20 @30", "hexagon R=40"], "mirror")
+    return res
+
+
+def _windows_case(torch, mf, img, img_np, reps, check_oracle, log, fps, ofps, names, boundary):
+    """One window_filter call over `fps` against one plain call per window,
+    and the same windows forced into one pass."""
     stream = torch.cuda.current_stream()
-    fps = [mf.Footprint.disc(r) for r in radii]
-    singles = [torch.empty_like(img) for _ in radii]
-    multi = [torch.empty_like(img) for _ in radii]
+    singles = [torch.empty_like(img) for _ in fps]
+    multi = [torch.empty_like(img) for _ in fps]
 
     def run_singles():
         for f, o in zip(fps, singles):
-            mf.median_filter(img, f, "clamp", out=o)
+            mf.median_filter(img, f, boundary, out=o)
 
     run_singles()
-    mf.window_filter(img, fps, "clamp", outs=multi)
+    mf.window_filter(img, fps, boundary, outs=multi)
     t_single = float(np.median(_time_events(torch, run_singles, stream, reps)))
     t_multi = float(np.median(_time_events(
-        torch, lambda: mf.window_filter(img, fps, "clamp", outs=multi), stream, reps)))
-    mism = sum(int((a != b).sum()) for a, b in zip(singles, multi))
+        torch, lambda: mf.window_filter(img, fps, boundary, outs=multi), stream, reps)))
+    bits = (lambda t: t.view(torch.int32)) if img.dtype == torch.float32 else (lambda t: t)
+    mism = sum(int((bits(a) != bits(b)).sum()) for a, b in zip(singles, multi))
     mf.set_window_fusion(True)
     try:
-        fused = [torch.empty_like(img) for _ in radii]
+        fused = [torch.empty_like(img) for _ in fps]
         t_fused = float(np.median(_time_events(
-            torch, lambda: mf.window_filter(img, fps, "clamp", outs=fused), stream, reps)))
+            torch, lambda: mf.window_filter(img, fps, boundary, outs=fused), stream, reps)))
     finally:
         mf.set_window_fusion(False)
-    mism += sum(int((a != b).sum()) for a, b in zip(singles, fused))
-    res = {"radii": list(radii), "single_calls_ms": t_single, "one_call_ms": t_multi,
+    mism += sum(int((bits(a) != bits(b)).sum()) for a, b in zip(singles, fused))
+    res = {"windows": names, "boundary": boundary, "dtype": str(img.dtype).replace("torch.", ""),
+           "size": [int(img.shape[1]), int(img.shape[0])],
+           "single_calls_ms": t_single, "one_call_ms": t_multi,
            "speedup": t_single / t_multi, "all_in_one_pass_ms": t_fused,
            "mismatches_multi_vs_single": mism}
     if check_oracle:
-        got = [o.cpu().numpy() for o in multi]
-        res["oracle_mismatches"] = sum(_oracle_sample(img_np, OF.disc(r), g, 700, 200 + r)
-                                       for r, g in zip(radii, got))
-        res["oracle_checked_px"] = 700 * len(radii)
-    log(f"# windows {list(radii)}: {len(radii)} plain calls {t_single:.2f} ms, "
+        import oracle
+        h, w = img_np.shape
+        rng = np.random.default_rng(200 + len(names))
+        bad = 0
+        for ofp, o in zip(ofps, multi):
+            xs, ys = rng.integers(0, w, 500), rng.integers(0, h, 500)
+            exp = oracle.filter_points(img_np, ofp, xs, ys, boundary,
+                                       nthreads=oracle.default_threads())
+            got = o.cpu().numpy()[ys, xs]
+            bad += int((got.view(np.uint8).reshape(500, -1) != exp.view(np.uint8).reshape(500, -1))
+                       .any(axis=1).sum())
+        res["oracle_mismatches"] = bad
+        res["oracle_checked_px"] = 500 * len(names)
+    log(f"# windows {names}: {len(names)} plain calls {t_single:.2f} ms, "
         f"one call {t_multi:.2f} ms, all in one pass {t_fused:.2f} ms")
     return res
 

@@ -195,3 +195,26 @@ def test_radii_full_size(mf, oracle_mod, radii, fused):
         xs, ys = rng.integers(0, S, 1000), rng.integers(0, S, 1000)
         assert np.array_equal(got[ys, xs], oracle_mod.filter_points(img, OF.disc(r), xs, ys,
                                                                     "clamp")), r
+
+
+def test_lognormal_f32_three_shapes_full_size(mf, oracle_mod):
+    """The float workload: one 3840x2160 log-normal plane with +-1e6
+    outliers, disc r=48, ellipse 60x20 at 30 degrees and hexagon R=40 in one
+    call (mirror), which the default grouping runs as one pass: every pixel
+    equals the single-window filter bit for bit, and 400 seeded pixels per
+    plane equal the oracle."""
+    img = np.ascontiguousarray(workloads.lognormal_f32(3840, 2160, planes=1, seed=2)[0])
+    d = dev(img)
+    wins = [(mf.Footprint.disc(48), OF.disc(48)),
+            (mf.Footprint.ellipse(60, 20, 30), OF.ellipse(60, 20, 30)),
+            (mf.Footprint.regular_polygon(6, 40), OF.regular_polygon(6, 40))]
+    outs = mf.window_filter(d, [w[0] for w in wins], "mirror")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(29)
+    h, w = img.shape
+    for (fp, ofp), o in zip(wins, outs):
+        got = o.cpu().numpy()
+        single = mf.median_filter(d, fp, "mirror").cpu().numpy()
+        assert same(got, single)
+        xs, ys = rng.integers(0, w, 400), rng.integers(0, h, 400)
+        assert same(got[ys, xs], oracle_mod.filter_points(img, ofp, xs, ys, "mirror"))
