@@ -261,7 +261,9 @@ int median_filter_windows(const void* img, int w, int h, size_t stride_bytes, in
   // walks see -- a small window in a large box crosses the extra box pixels
   // as non-members at every step.  kFuse separates the measured cases at
   // 4096^2 uint16 (one pass faster than separate calls: radii 24+32, 32+48,
-  // 28+32+40, 24+32+40; slower: 8+16, 8+32, 16+64, 8+16+32).
+  // 28+32+40, 24+32+40; slower: 8+16, 8+32, 16+64, 8+16+32) and keeps the
+  // float32 disc 48 + ellipse 60x20 + hexagon R=40 set in one pass (1.19x
+  // at 3840x2160).
   constexpr double kFuse = 0.25;
   int order[MF_MAX_RANK_OUTPUTS];
   long long boxT[MF_MAX_RANK_OUTPUTS];
