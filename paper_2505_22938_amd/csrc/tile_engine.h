@@ -1014,9 +1014,9 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   }
   if (a.counters) {
     // lane-parallel groups differ per lane: sum over the wave
-    unsigned long long gsum = (unsigned long long)groups;
-    for (int d = 32; d >= 1; d >>= 1) gsum += __shfl_xor(gsum, d, 64);
-    if (lane == 0) atomicAdd(&a.counters[CNT_GROUPS], gsum);
+    // (one atomic per lane: a cross-lane reduction here would keep lane
+    // indices live through the whole tile, and they spill)
+    if (groups) atomicAdd(&a.counters[CNT_GROUPS], (unsigned long long)groups);
   }
   return false;
 }
