@@ -85,7 +85,11 @@ int mf_footprint_disc_limit(long long limit, mf_footprint** out);
 int mf_footprint_ellipse(double a, double b, double theta_deg, mf_footprint** out);
 
 /* Convex polygon from n_vertices (x, y) pairs in `xy`, either winding;
- * inclusive: points within 1e-9 * (max vertex radius) of an edge are members. */
+ * inclusive: points within 1e-9 * (max vertex radius) of an edge are members.
+ * Collinear consecutive vertices are allowed.  A vertex list that is not
+ * convex (a turn against the winding, or a star that winds more than once),
+ * has zero area, a repeated vertex or a non-finite coordinate returns
+ * MF_ERR_INVALID_ARG. */
 int mf_footprint_polygon(const double* xy, int n_vertices, mf_footprint** out);
 
 /* Regular polygon: vertices at angles rot_deg + 360 k / n_sides on a circle
@@ -109,9 +113,22 @@ void mf_footprint_destroy(mf_footprint* fp);
  *
  * Filters one plane: out(x, y) = rank-(N-1)/2 element of the window values
  * around (x, y).  img/out: device pointers, stride_bytes as above; dtype is
- * an mf_dtype and boundary an mf_boundary.  Scratch memory, if the chosen
- * tiling needs it, is allocated by the library on first use per device and
- * kept for later calls.
+ * an mf_dtype and boundary an mf_boundary.
+ *
+ * Memory: the first call with a footprint on a device uploads its span
+ * table (kept until mf_footprint_destroy).  Large windows (global-scratch
+ * tiles) use a scratch buffer cached per (device, stream), allocated on first
+ * need and replaced by a larger one when a later call on that stream needs
+ * more (about 0.3-1 MB per concurrent tile: 130 MB for radius 100 uint16,
+ * twice that for float32); mf_release_scratch frees it.
+ *
+ * Graph capture: while `stream` is being captured the call never allocates.
+ * It returns MF_ERR_UNSUPPORTED instead if the footprint's table is not yet
+ * on the device or the stream's scratch is too small, so a call to be
+ * captured needs one uncaptured call with the same footprint, dtype and an
+ * image at least as large on that stream first.  Scratch used by a captured
+ * call stays allocated (and is not reused for a larger size) until
+ * mf_release_scratch.
  * ------------------------------------------------------------------------ */
 int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
                   const mf_footprint* fp, int boundary, void* out, hipStream_t stream);
@@ -124,9 +141,10 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * General rank outputs (paper, Discussion "Multi-Parameter Filtering": one
- * ordinal transform can serve several percentiles; Conclusion and the
- * varying-percentile figure: the percentile may change across the image).
+ * General rank outputs (paper, Limitations and Future Work > Future Work >
+ * Multi-Parameter Filtering: one ordinal transform can serve several
+ * percentiles; Conclusion and the varying-percentile figure: the percentile
+ * may change across the image).
  *
  * median_filter_ranks writes `nouts` planes (1..MF_MAX_RANK_OUTPUTS) from
  * one pass: each tile's box is loaded and sorted once, then its bands run
@@ -160,9 +178,10 @@ int median_filter_rank_map(const void* img, int w, int h, size_t stride_bytes, i
                            size_t rank_map_stride_bytes, void* out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Several windows from one ordinal transform (paper, Discussion
- * "Multi-Parameter Filtering": one ordinal transform can serve filters of
- * several radii, as long as each tile's box holds all their windows).
+ * Several windows from one ordinal transform (paper, Limitations and Future
+ * Work > Future Work > Multi-Parameter Filtering: one ordinal transform can
+ * serve filters of several radii, as long as each tile's box holds all their
+ * windows).
  *
  * median_filter_windows writes `nouts` planes (1..MF_MAX_RANK_OUTPUTS) of
  * img, each with its own footprint: plane q (outs[q].out, same shape and
@@ -281,6 +300,12 @@ int median_filter_batched(const mf_image_desc* descs, int n, hipStream_t stream)
  * calls from every thread.
  * ------------------------------------------------------------------------ */
 int mf_set_tile_override(int tile_w, int tile_h);
+
+/* Free every scratch buffer the plain, general-rank and learned filters have
+ * cached (all devices and streams).  Waits for each device to go idle.  No
+ * filter call may be running and no graph captured around one may be
+ * replayed afterwards (its scratch is gone); later calls allocate again. */
+int mf_release_scratch(void);
 
 /* Work counters of the tile engine, for the benchmark's work model.
  * enable = 1: allocate (once) and zero ten device counters that later calls

@@ -15,6 +15,10 @@ checked:
 * pinball (quantile) loss: rho_tau(u) = u (tau - [u < 0]), u = target - pred,
   averaged over cells; tau_lo = 0.02 for lo, tau_hi = 0.98 for hi.
 * backward passes by the chain rule, written out per layer.
+* Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization", 2015,
+  Algorithm 1): exponential moving averages of the gradient and of its
+  square, each divided by its bias correction 1 - beta^t, and the step
+  -lr * mhat / (sqrt(vhat) + eps).
 """
 
 from __future__ import annotations
@@ -100,6 +104,17 @@ def backward(params, cache, dout):
         grads[li] = (dw, db)
         d = dx
     return grads
+
+
+def adam_step(p, m, v, g, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update at step number `step` (1-based) in float64; returns the
+    new (p, m, v).  m and v start at zero before step 1."""
+    p, m, v, g = (np.asarray(a, dtype=np.float64) for a in (p, m, v, g))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** step)
+    vhat = v / (1.0 - b2 ** step)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
 def cell_features(img: np.ndarray, radius: int, maxval: float) -> np.ndarray:

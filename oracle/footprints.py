@@ -78,6 +78,20 @@ def polygon(vertices) -> np.ndarray:
     if area2 == 0:
         raise ValueError("degenerate polygon")
     orient = 1.0 if area2 > 0 else -1.0
+    # convex: no turn against the winding, and one full turn in total (a
+    # self-intersecting star turns the same way everywhere but winds twice)
+    total = 0.0
+    for i in range(n):
+        (ax, ay), (bx, by), (cx, cy) = V[i], V[(i + 1) % n], V[(i + 2) % n]
+        ux, uy, vx, vy = bx - ax, by - ay, cx - bx, cy - by
+        if ux == 0 and uy == 0:
+            raise ValueError("repeated vertex")
+        cr = ux * vy - uy * vx
+        if orient * cr < -1e-12 * math.hypot(ux, uy) * math.hypot(vx, vy):
+            raise ValueError("polygon is not convex")
+        total += math.atan2(orient * cr, ux * vx + uy * vy)
+    if abs(total - 2 * math.pi) > 1e-6:
+        raise ValueError("polygon is not convex (it winds more than once)")
     scale = max(math.hypot(x, y) for x, y in V)
     tol = 1e-9 * max(scale, 1.0)
     R = int(math.ceil(scale)) + 1

@@ -59,6 +59,7 @@ def lib():
         "median_filter_windows": ([P, I, I, SZ, I, I, P, I, P], I),
         "mf_set_window_fusion": ([I], I),
         "mf_set_tile_override": ([I, I], I),
+        "mf_release_scratch": ([], I),
         "mf_query_plan": ([I, I, I, P, IP, IP, IP, IP, IP], I),
         "mf_work_counters": ([I, P], I),
         "mf_autotune": ([P, I, I, SZ, I, P, I, P, P, I, IP, IP,
@@ -363,6 +364,12 @@ def set_window_fusion(all_in_one_pass: bool):
 
 def set_tile_override(tile_w: int = 0, tile_h: int = 0):
     _check("mf_set_tile_override", lib().mf_set_tile_override(int(tile_w), int(tile_h)))
+
+
+def release_scratch():
+    """Free the scratch buffers the filters cache per (device, stream); waits
+    for the devices to go idle."""
+    _check("mf_release_scratch", lib().mf_release_scratch())
 
 
 def work_counters(enable: int):

@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "mf_internal.h"
@@ -439,7 +440,10 @@ int mf_cnn_targets(const void* med, int w, int h, size_t stride_bytes, int dtype
 int mf_cnn_adam(float* p, float* m, float* v, const float* grad, int n, float lr, float b1,
                 float b2, float eps, int step, void* p_bf16, hipStream_t stream) {
   if (!p || !m || !v || !grad || n <= 0 || step < 1) return MF_ERR_INVALID_ARG;
-  const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+  // bias corrections 1 - beta^t in double: in float32, 1 - powf(0.999f, 2)
+  // keeps only a few correct bits (the power is within one ulp of 1)
+  const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
   hipLaunchKernelGGL(mf::adam_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, m, v, grad,
                      n, lr, b1, b2, eps, bc1, bc2, static_cast<uint16_t*>(p_bf16));
   return launch_ok();

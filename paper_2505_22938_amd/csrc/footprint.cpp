@@ -159,6 +159,24 @@ int mf_footprint_polygon(const double* xy, int n, mf_footprint** out) {
   if (area2 == 0) return MF_ERR_INVALID_ARG;
   if (scale > kMaxExtent) return MF_ERR_UNSUPPORTED;
   const double orient = area2 > 0 ? 1.0 : -1.0;
+  // Convexity: every turn between consecutive edges goes the way of the
+  // winding (or straight on), and the turns add up to one full turn (a
+  // self-intersecting star turns the same way at every vertex but winds
+  // more than once).  The edge half-planes would otherwise describe a
+  // different set than the polygon.
+  {
+    double turn = 0;
+    for (int i = 0; i < n; ++i) {
+      const int j = (i + 1) % n, k = (i + 2) % n;
+      const double ax = xy[2 * j] - xy[2 * i], ay = xy[2 * j + 1] - xy[2 * i + 1];
+      const double bx = xy[2 * k] - xy[2 * j], by = xy[2 * k + 1] - xy[2 * j + 1];
+      const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
+      const double mag = std::hypot(ax, ay) * std::hypot(bx, by);
+      if (orient * cr < -1e-12 * mag) return MF_ERR_INVALID_ARG;
+      turn += std::atan2(orient * cr, dt);
+    }
+    if (std::fabs(turn - 2 * M_PI) > 1e-6) return MF_ERR_INVALID_ARG;
+  }
   const double tol = 1e-9 * std::max(scale, 1.0);
   // Inward edge normals, normalised, so the test is a signed distance.
   std::vector<double> nx(n), ny(n), off(n);
@@ -230,13 +248,19 @@ void mf_footprint_destroy(mf_footprint* fp) {
 
 namespace mf {
 
-int footprint_device_table(const mf_footprint* fp, int device, const void** table) {
+int footprint_device_table(const mf_footprint* fp, int device, const void** table,
+                           hipStream_t stream) {
   std::lock_guard<std::mutex> lock(fp->mu);
   for (auto& d : fp->dev)
     if (d.device == device) {
       *table = d.ptr;
       return MF_OK;
     }
+  // the upload allocates and copies synchronously: not while the caller's
+  // stream is being captured into a graph
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return MF_ERR_HIP;
+  if (cap != hipStreamCaptureStatusNone) return MF_ERR_UNSUPPORTED;
   const size_t nr = fp->row_lo.size(), nc = fp->col_lo.size();
   std::vector<int16_t> host(2 * (nr + nc));
   for (size_t i = 0; i < nr; ++i) {

@@ -444,7 +444,7 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
                      size_t stride, int dtype, const mf_footprint* fp, int boundary, void* out,
                      unsigned long long* fallback_px, hipStream_t s, const LearnedPlan& lp) {
   const void* table = nullptr;
-  int rc = mf::footprint_device_table(fp, lp.dev, &table);
+  int rc = mf::footprint_device_table(fp, lp.dev, &table, s);
   if (rc) return rc;
   mf::ImageDesc a = lp.br, f = lp.fb;
   const int rank = (fp->taps - 1) / 2;

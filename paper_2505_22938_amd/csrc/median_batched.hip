@@ -234,7 +234,7 @@ int mf_plan_create(const mf_image_desc* descs, int n, const char* tune_cache_pat
       continue;
     }
     const void* table = nullptr;
-    if ((rc = footprint_device_table(e.fp, dev, &table)) ||
+    if ((rc = footprint_device_table(e.fp, dev, &table, nullptr)) ||
         (rc = choose_plan(e.dtype, e.fp, di.lds_max, kMaxItems, &hd[i]))) {
       mf_plan_destroy(p);
       return rc;

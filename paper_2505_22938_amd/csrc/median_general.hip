@@ -127,7 +127,7 @@ int launch_window_pass(const void* img, int w, int h, size_t stride_bytes, int d
     return MF_OK;
   }
   const void* table0 = nullptr;
-  if ((rc = footprint_device_table(outs[idx[0]].footprint, dev, &table0))) return rc;
+  if ((rc = footprint_device_table(outs[idx[0]].footprint, dev, &table0, stream))) return rc;
   bind_image(&a, img, w, h, stride_bytes, dtype, &hull, boundary, 0, table0);
   a.out = outs[idx[0]].out;
   a.nq = n;
@@ -136,7 +136,7 @@ int launch_window_pass(const void* img, int w, int h, size_t stride_bytes, int d
     const mf_window_output& o = outs[idx[q]];
     const mf_footprint* fp = o.footprint;
     const void* table = nullptr;
-    if ((rc = footprint_device_table(fp, dev, &table))) return rc;
+    if ((rc = footprint_device_table(fp, dev, &table, stream))) return rc;
     PlaneFp& pf = a.pfp[q];
     pf.spans = static_cast<const short2*>(table);
     pf.dx_min = fp->dx_min;
@@ -202,7 +202,7 @@ int median_filter_ranks(const void* img, int w, int h, size_t stride_bytes, int 
   int rc = device_info(dev, &di);
   if (rc) return rc;
   const void* table = nullptr;
-  if ((rc = footprint_device_table(fp, dev, &table))) return rc;
+  if ((rc = footprint_device_table(fp, dev, &table, stream))) return rc;
   ImageDesc a{};
   if ((rc = choose_plan(dtype, fp, di.lds_max, 33, &a, w, h, di.cus))) return rc;
   bind_image(&a, img, w, h, stride_bytes, dtype, fp, boundary, (fp->taps - 1) / 2, table);

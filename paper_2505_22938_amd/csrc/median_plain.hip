@@ -106,7 +106,7 @@ int launch_plain(const void* img, int w, int h, size_t stride_bytes, int dtype,
   int rc = device_info(dev, &di);
   if (rc) return rc;
   const void* table = nullptr;
-  rc = footprint_device_table(fp, dev, &table);
+  rc = footprint_device_table(fp, dev, &table, stream);
   if (rc) return rc;
   ImageDesc a{};
   rc = choose_plan(dtype, fp, di.lds_max, 33, &a, w, h, di.cus);
@@ -215,7 +215,7 @@ int mf_autotune(const void* img, int w, int h, size_t stride_bytes, int dtype,
   mf::DeviceInfo di;
   if ((rc = mf::device_info(dev, &di))) return rc;
   const void* table = nullptr;
-  if ((rc = mf::footprint_device_table(fp, dev, &table))) return rc;
+  if ((rc = mf::footprint_device_table(fp, dev, &table, stream))) return rc;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MF_ERR_HIP;
   float best = 1e30f;

@@ -129,8 +129,11 @@ void bind_image(ImageDesc* d, const void* img, int w, int h, size_t stride_bytes
 int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype,
                    const mf_footprint* fp, int boundary, const void* out);
 
-// Global scratch cached per (device, stream).
+// Global scratch cached per (device, stream); never allocates while the
+// stream is capturing (MF_ERR_UNSUPPORTED instead).  release_scratch frees
+// every cached buffer (mf_release_scratch).
 int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out);
+int release_scratch();
 
 // Tuned tile shapes, keyed by dtype and footprint.
 std::string tune_key(int dtype, const mf_footprint* fp);
@@ -160,7 +163,9 @@ void get_override(int* tw, int* th);
 
 // Upload (once per device) and return the device span table of `fp`:
 // [row (lo,hi) pairs as int16][column (lo,hi) pairs as int16].
-int footprint_device_table(const mf_footprint* fp, int device, const void** table);
+// MF_ERR_UNSUPPORTED if the table is not there yet and `stream` is capturing.
+int footprint_device_table(const mf_footprint* fp, int device, const void** table,
+                           hipStream_t stream);
 
 inline int elem_size(int dtype) { return dtype == MF_U8 ? 1 : dtype == MF_U16 ? 2 : 4; }
 

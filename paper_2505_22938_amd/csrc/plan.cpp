@@ -393,32 +393,67 @@ struct ScratchEntry {
   hipStream_t stream;
   void* ptr;
   size_t bytes;
+  bool captured;   // a graph captured on the stream may still use ptr
 };
 std::mutex g_scratch_mu;
 std::vector<ScratchEntry> g_scratch;
+std::vector<std::pair<int, void*>> g_retired;   // outgrown but possibly captured
 }  // namespace
 
+// Cached per (device, stream).  A stream under graph capture never
+// allocates: a buffer that is already large enough is used (and kept alive
+// until mf_release_scratch, since the graph refers to it), anything else
+// returns MF_ERR_UNSUPPORTED.  Outside capture a buffer that is too small is
+// replaced; if a captured graph may refer to the old one it is retired, not
+// freed.
 int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return MF_ERR_HIP;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   for (auto& e : g_scratch) {
     if (e.dev == dev && e.stream == stream) {
       if (e.bytes < bytes) {
+        if (capturing) return MF_ERR_UNSUPPORTED;
         if (hipStreamSynchronize(stream) != hipSuccess) return MF_ERR_HIP;
-        (void)hipFree(e.ptr);
+        if (e.captured) g_retired.push_back({dev, e.ptr});
+        else (void)hipFree(e.ptr);
         e.ptr = nullptr;
         e.bytes = 0;
+        e.captured = false;
         if (hipMalloc(&e.ptr, bytes) != hipSuccess) return MF_ERR_NOMEM;
         e.bytes = bytes;
       }
+      e.captured = e.captured || capturing;
       *out = e.ptr;
       return MF_OK;
     }
   }
+  if (capturing) return MF_ERR_UNSUPPORTED;
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return MF_ERR_NOMEM;
-  g_scratch.push_back({dev, stream, p, bytes});
+  g_scratch.push_back({dev, stream, p, bytes, false});
   *out = p;
   return MF_OK;
+}
+
+int release_scratch() {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return MF_ERR_HIP;
+  if (hipDeviceSynchronize() != hipSuccess) return MF_ERR_HIP;
+  int rc = MF_OK;
+  auto drop = [&](int dev, void* ptr) {
+    if (hipSetDevice(dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipFree(ptr) != hipSuccess)
+      rc = MF_ERR_HIP;
+  };
+  for (auto& e : g_scratch) drop(e.dev, e.ptr);
+  for (auto& r : g_retired) drop(r.first, r.second);
+  g_scratch.clear();
+  g_retired.clear();
+  (void)hipSetDevice(cur);
+  return rc;
 }
 
 // ------------------------------------------------------------------ tuning table
@@ -505,6 +540,8 @@ int tune_cache_save(const char* path) {
 }
 
 }  // namespace mf
+
+extern "C" int mf_release_scratch(void) { return mf::release_scratch(); }
 
 extern "C" int mf_set_tile_override(int tile_w, int tile_h) {
   if (tile_w < 0 || tile_h < 0 || (tile_w == 0) != (tile_h == 0)) return MF_ERR_INVALID_ARG;

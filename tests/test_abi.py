@@ -3,6 +3,7 @@ symbol, builds the same footprints as the oracle's rasteriser, and rejects
 bad arguments before touching the GPU.  No GPU needed."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -80,6 +81,35 @@ def test_footprint_errors():
     assert L.mf_footprint_ellipse(0.0, 1.0, 0.0, ctypes.byref(h)) == -1
     assert L.mf_footprint_regular_polygon(2, 5.0, 0.0, ctypes.byref(h)) == -1
     assert L.mf_status_string(-3) == b"MF_ERR_UNSUPPORTED"
+
+
+NON_CONVEX = {
+    # a dart: 49 lattice points, but its edge half-planes hold only 17
+    "dart": [(0, -6), (6, 6), (0, 0), (-6, 6)],
+    # a pentagram: every turn goes the same way, but it winds twice
+    "star": [(10 * math.cos(math.radians(90 + 144 * k)), 10 * math.sin(math.radians(90 + 144 * k)))
+             for k in range(5)],
+    "repeated vertex": [(0, -3), (3, 2), (3, 2), (-3, 2)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(NON_CONVEX))
+def test_non_convex_polygon_rejected(name):
+    v = NON_CONVEX[name]
+    flat = (ctypes.c_double * (2 * len(v)))(*[c for p in v for c in p])
+    h = ctypes.c_void_p()
+    assert mf.lib().mf_footprint_polygon(flat, len(v), ctypes.byref(h)) == -1
+    with pytest.raises(ValueError):
+        OF.polygon(v)
+
+
+def test_polygon_collinear_vertices_and_winding():
+    # a square with an extra vertex in the middle of one side, both windings
+    sq = [(-4, -4), (0, -4), (4, -4), (4, 4), (-4, 4)]
+    for v in (sq, sq[::-1]):
+        a = mf.Footprint.polygon(v)
+        assert _set(a) == {tuple(int(c) for c in p) for p in OF.polygon(v)}
+        assert a.taps == 81
 
 
 def test_argument_validation_is_host_side():

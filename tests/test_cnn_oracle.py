@@ -102,3 +102,47 @@ def test_cell_features_and_targets():
 def test_bf16_round():
     assert cnn.bf16_round(np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9])).tolist() == \
         [1.0, 1.0, 1.0 + 2 ** -7]
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g from zero moments, m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected moments are exactly g and
+    g^2 and every step moves p by -lr * g / (|g| + eps), whatever b1 and b2
+    are.  Tiny gradients (|g| ~ eps) separate eps outside the root from
+    eps inside it."""
+    g = np.array([1.0, -2.5, 3e-4, -1e-8, 2e-8, 0.0])
+    lr, eps = 1e-3, 1e-8
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.75)):
+        p = np.array([0.3, -1.0, 2.0, 5.0, -5.0, 7.0])
+        m = np.zeros_like(g)
+        v = np.zeros_like(g)
+        p0 = p.copy()
+        for t in range(1, 8):
+            p, m, v = cnn.adam_step(p, m, v, g, lr, t, b1=b1, b2=b2, eps=eps)
+            assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-12, atol=0)
+            assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+            exp = p0 - t * lr * g / (np.abs(g) + eps)
+            assert np.allclose(p, exp, rtol=1e-12, atol=1e-17)
+    # |g| = eps: the step is half of lr (eps added under the root would give about 1e-4 lr)
+    p, _, _ = cnn.adam_step(np.zeros(1), np.zeros(1), np.zeros(1), np.array([1e-8]), 1.0, 1)
+    assert p[0] == pytest.approx(-0.5, rel=1e-12)
+
+
+def test_adam_two_gradients_weighted_average():
+    """Two steps with gradients g1 then g2: the bias-corrected moments are the
+    normalised weighted averages (b1 g1 + g2) / (1 + b1) and
+    (b2 g1^2 + g2^2) / (1 + b2) (sum of a geometric series of weights)."""
+    b1, b2, lr, eps = 0.9, 0.999, 0.1, 1e-8
+    g1, g2 = np.array([1.0, -2.0, 0.5]), np.array([3.0, 1.0, -0.5])
+    p, m, v = cnn.adam_step(np.zeros(3), np.zeros(3), np.zeros(3), g1, lr, 1)
+    p1 = p.copy()
+    p, m, v = cnn.adam_step(p, m, v, g2, lr, 2)
+    mhat = (b1 * g1 + g2) / (1 + b1)
+    vhat = (b2 * g1 ** 2 + g2 ** 2) / (1 + b2)
+    assert np.allclose(p - p1, -lr * mhat / (np.sqrt(vhat) + eps), rtol=1e-12, atol=0)
+
+
+def test_adam_zero_gradient_keeps_parameters():
+    p = np.array([1.0, -2.0])
+    out, m, v = cnn.adam_step(p, np.zeros(2), np.zeros(2), np.zeros(2), 0.5, 1)
+    assert np.array_equal(out, p) and np.all(m == 0) and np.all(v == 0)

@@ -258,3 +258,48 @@ def test_autotune_records_shape_and_cache_round_trip(mf, oracle_mod, tmp_path):
     mf.tune_cache_load(path)
     assert (mf.query_plan(300, 210, mf.MF_U16, fp)["tile_w"],
             mf.query_plan(300, 210, mf.MF_U16, fp)["tile_h"]) == (tw, th)
+
+
+def test_graph_capture_after_warm_call_and_release(mf, oracle_mod):
+    """A plain call is captured into a graph once one uncaptured call on the
+    same stream has uploaded its footprint and sized its scratch (radius 100:
+    global-scratch tiles).  Replays, with eager work in between, match the
+    eager outputs and the oracle.  A footprint never used on the device
+    cannot be captured (MF_ERR_UNSUPPORTED, nothing enqueued).  After
+    mf_release_scratch the next call allocates again and is still exact."""
+    img = workloads.natural_u16(400, 300, seed=31)
+    d_img = to_dev(img)
+    fps = [mf.Footprint.disc(100), mf.Footprint.disc(8)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        eager = [mf.median_filter(d_img, fp, "clamp") for fp in fps]
+    s.synchronize()
+    outs = [torch.empty_like(d_img) for _ in fps]
+    fresh = mf.Footprint.disc(5)
+    status = None
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for fp, o in zip(fps, outs):
+            mf.median_filter(d_img, fp, "clamp", out=o)
+        try:
+            mf.median_filter(d_img, fresh, "clamp")
+        except mf.MedianFilterError as e:
+            status = e.status
+    assert status == -3
+    for rep in range(3):
+        for o in outs:
+            o.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+        # eager work between replays
+        mf.median_filter(d_img, mf.Footprint.disc(3), "mirror")
+        torch.cuda.synchronize()
+    exp = oracle_mod.filter(img, OF.disc(100), "clamp")
+    assert_same(outs[0].cpu().numpy(), exp, "captured r=100")
+    del g
+    torch.cuda.synchronize()
+    mf.release_scratch()
+    got = run(mf, img, mf.Footprint.disc(100), "clamp")
+    assert_same(got, exp, "after release")
