@@ -50,7 +50,8 @@ typedef enum {
   MF_ERR_ALIAS = -2,       /* out overlaps img                                   */
   MF_ERR_UNSUPPORTED = -3, /* footprint not row- and column-convex, or too big   */
   MF_ERR_NOMEM = -4,       /* device or host allocation failed                   */
-  MF_ERR_HIP = -5          /* a HIP runtime call or kernel launch failed         */
+  MF_ERR_HIP = -5,         /* a HIP runtime call or kernel launch failed         */
+  MF_ERR_SCRATCH_LIMIT = -6 /* needs more than the fixed scratch buffer holds    */
 } mf_status;
 
 /* Human-readable name of a status code (static storage; never NULL). */
@@ -139,6 +140,33 @@ int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
 int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int dtype,
                        const mf_footprint* fp, int boundary, int rank, void* out,
                        hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free median filter, for callers that cannot allocate device
+ * memory: code under graph capture, tight serving loops, hosts that forbid
+ * hipMalloc.
+ *
+ * Same arguments, result and kernels as median_filter.  It never calls
+ * hipMalloc, hipFree or an allocating library routine: the footprint's span
+ * table and the global-scratch sort slots of large windows live in one
+ * fixed device array of MF_NOALLOC_SCRATCH_BYTES per GPU (64 KiB for the
+ * span table, the rest for sort slots), held from the first call on that
+ * GPU until the process ends.  The span table is written into it by a small
+ * kernel on `stream` at every call (no host-to-device copy).  A large
+ * window's persistent grid is shrunk to the sort slots that fit the array
+ * (speed only; the output is unchanged); MF_ERR_SCRATCH_LIMIT if not even
+ * one slot fits (no plan of this library needs that much today).
+ *
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents; calls on one stream are ordered, but calls that overlap on one
+ * GPU (other streams, other host threads) race on it and must be
+ * serialised by the caller.  The first call on a GPU looks the array up
+ * (hipGetSymbolAddress) with that GPU current.
+ * ------------------------------------------------------------------------ */
+#define MF_NOALLOC_SCRATCH_BYTES ((size_t)128 * 1024 * 1024 + (size_t)64 * 1024)
+int median_filter_noalloc(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          const mf_footprint* fp, int boundary, void* out,
+                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * General rank outputs (paper, Limitations and Future Work > Future Work >

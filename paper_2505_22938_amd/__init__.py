@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libmedianfilter.so")
 MF_U8, MF_U16, MF_F32 = 0, 1, 2
 MF_CLAMP, MF_MIRROR = 0, 1
 STATUS = {0: "MF_OK", -1: "MF_ERR_INVALID_ARG", -2: "MF_ERR_ALIAS", -3: "MF_ERR_UNSUPPORTED",
-          -4: "MF_ERR_NOMEM", -5: "MF_ERR_HIP"}
+          -4: "MF_ERR_NOMEM", -5: "MF_ERR_HIP", -6: "MF_ERR_SCRATCH_LIMIT"}
 BOUNDARY = {"clamp": MF_CLAMP, "mirror": MF_MIRROR}
 
 _lib = None
@@ -54,6 +54,7 @@ def lib():
         "mf_footprint_destroy": ([P], None),
         "median_filter": ([P, I, I, SZ, I, P, I, P, P], I),
         "median_filter_rank": ([P, I, I, SZ, I, P, I, I, P, P], I),
+        "median_filter_noalloc": ([P, I, I, SZ, I, P, I, P, P], I),
         "median_filter_ranks": ([P, I, I, SZ, I, P, I, P, I, P], I),
         "median_filter_rank_map": ([P, I, I, SZ, I, P, I, P, SZ, P, P], I),
         "median_filter_windows": ([P, I, I, SZ, I, I, P, I, P], I),
@@ -239,6 +240,21 @@ def median_filter(img, fp: Footprint, boundary: str = "clamp", out=None, rank: i
                                   fp.handle, BOUNDARY[boundary], int(rank),
                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
         _check("median_filter_rank", rc)
+    return out
+
+
+def median_filter_noalloc(img, fp: Footprint, out, boundary: str = "clamp", stream=None):
+    """median_filter without any device allocation: `out` (same shape, dtype
+    and strides as `img`) must be given; span table and sort scratch come
+    from the library's fixed per-GPU array (calls that overlap on one GPU
+    race on it)."""
+    code, es, w, h, stride_bytes = _plane_args(img)
+    if out.shape != img.shape or out.dtype != img.dtype or out.stride() != img.stride():
+        raise ValueError("out must match img in shape, dtype and strides")
+    rc = lib().median_filter_noalloc(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes, code,
+                                     fp.handle, BOUNDARY[boundary],
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check("median_filter_noalloc", rc)
     return out
 
 

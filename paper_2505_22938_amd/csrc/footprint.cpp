@@ -248,6 +248,23 @@ void mf_footprint_destroy(mf_footprint* fp) {
 
 namespace mf {
 
+size_t footprint_span_table_len(const mf_footprint* fp) {
+  return 2 * (fp->row_lo.size() + fp->col_lo.size());
+}
+
+size_t footprint_span_table(const mf_footprint* fp, int16_t* dst) {
+  const size_t nr = fp->row_lo.size(), nc = fp->col_lo.size();
+  for (size_t i = 0; i < nr; ++i) {
+    dst[2 * i] = (int16_t)fp->row_lo[i];
+    dst[2 * i + 1] = (int16_t)fp->row_hi[i];
+  }
+  for (size_t i = 0; i < nc; ++i) {
+    dst[2 * (nr + i)] = (int16_t)fp->col_lo[i];
+    dst[2 * (nr + i) + 1] = (int16_t)fp->col_hi[i];
+  }
+  return 2 * (nr + nc);
+}
+
 int footprint_device_table(const mf_footprint* fp, int device, const void** table,
                            hipStream_t stream) {
   std::lock_guard<std::mutex> lock(fp->mu);
@@ -261,16 +278,8 @@ int footprint_device_table(const mf_footprint* fp, int device, const void** tabl
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return MF_ERR_HIP;
   if (cap != hipStreamCaptureStatusNone) return MF_ERR_UNSUPPORTED;
-  const size_t nr = fp->row_lo.size(), nc = fp->col_lo.size();
-  std::vector<int16_t> host(2 * (nr + nc));
-  for (size_t i = 0; i < nr; ++i) {
-    host[2 * i] = (int16_t)fp->row_lo[i];
-    host[2 * i + 1] = (int16_t)fp->row_hi[i];
-  }
-  for (size_t i = 0; i < nc; ++i) {
-    host[2 * (nr + i)] = (int16_t)fp->col_lo[i];
-    host[2 * (nr + i) + 1] = (int16_t)fp->col_hi[i];
-  }
+  std::vector<int16_t> host(footprint_span_table_len(fp));
+  footprint_span_table(fp, host.data());
   void* p = nullptr;
   if (hipMalloc(&p, host.size() * sizeof(int16_t)) != hipSuccess) return MF_ERR_NOMEM;
   if (hipMemcpy(p, host.data(), host.size() * sizeof(int16_t), hipMemcpyHostToDevice) !=

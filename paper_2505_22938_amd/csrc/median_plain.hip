@@ -77,7 +77,8 @@ unsigned long long* work_counters_ptr() { return g_counters; }
 
 // Launch one plain filter with a complete plan `a` (geometry + image bound);
 // a.nq > 0 selects the general-rank kernels.
-int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream) {
+int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream,
+                     unsigned char* ext_scratch, size_t ext_bytes) {
   a.counters = g_counters;
   KernelFn k = a.nq > 0 ? pick_general_kernel(a) : pick_kernel(a);
   (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -88,10 +89,17 @@ int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t str
   if (a.gs) {
     const int occ = std::max(1, std::min(2, di.lds_max / std::max(1, a.lds_bytes)));
     grid = std::min<long long>(ntiles, (long long)di.cus * occ);
-    void* scr = nullptr;
-    const int rc = get_scratch(dev, stream, (size_t)grid * (size_t)a.slot_bytes, &scr);
-    if (rc) return rc;
-    a.scratch = static_cast<unsigned char*>(scr);
+    if (ext_scratch) {
+      const long long fit = (long long)(ext_bytes / (size_t)a.slot_bytes);
+      if (fit < 1) return MF_ERR_SCRATCH_LIMIT;
+      grid = std::min(grid, fit);
+      a.scratch = ext_scratch;
+    } else {
+      void* scr = nullptr;
+      const int rc = get_scratch(dev, stream, (size_t)grid * (size_t)a.slot_bytes, &scr);
+      if (rc) return rc;
+      a.scratch = static_cast<unsigned char*>(scr);
+    }
   }
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), a.lds_bytes, stream, a);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
@@ -163,6 +171,7 @@ const char* mf_status_string(int s) {
     case MF_ERR_UNSUPPORTED: return "MF_ERR_UNSUPPORTED";
     case MF_ERR_NOMEM: return "MF_ERR_NOMEM";
     case MF_ERR_HIP: return "MF_ERR_HIP";
+    case MF_ERR_SCRATCH_LIMIT: return "MF_ERR_SCRATCH_LIMIT";
     default: return "MF_ERR_UNKNOWN";
   }
 }

@@ -147,8 +147,13 @@ unsigned long long* work_counters_ptr();
 
 // Plain-filter launch with a complete plan (median_plain.hip); a.nq > 0
 // runs the general-rank kernels (median_general.hip).
+// ext_scratch (non-null): a global-scratch plan takes its slots from this
+// buffer of ext_bytes bytes instead of the cached per-stream scratch, its
+// persistent grid shrunk to the slots that fit (MF_ERR_SCRATCH_LIMIT if not
+// even one does); nothing is allocated.
 using PlainKernelFn = void (*)(ImageDesc);
-int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream);
+int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t stream,
+                     unsigned char* ext_scratch = nullptr, size_t ext_bytes = 0);
 PlainKernelFn pick_general_kernel(const ImageDesc& d);
 // median_filter_windows: one pass for all windows (set by
 // mf_set_window_fusion) instead of grouping them by box size.
@@ -166,6 +171,10 @@ void get_override(int* tw, int* th);
 // MF_ERR_UNSUPPORTED if the table is not there yet and `stream` is capturing.
 int footprint_device_table(const mf_footprint* fp, int device, const void** table,
                            hipStream_t stream);
+// The same table on the host: 2 * (rows + columns) int16 values written to
+// `dst` (which holds at least that many); returns the count.
+size_t footprint_span_table(const mf_footprint* fp, int16_t* dst);
+size_t footprint_span_table_len(const mf_footprint* fp);
 
 inline int elem_size(int dtype) { return dtype == MF_U8 ? 1 : dtype == MF_U16 ? 2 : 4; }
 

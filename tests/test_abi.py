@@ -130,6 +130,15 @@ def test_argument_validation_is_host_side():
     assert L.median_filter(P(4096), 0, 8, 8, 0, fp.handle, 0, P(1 << 20), None) == 0
     # rank out of range
     assert L.median_filter_rank(P(4096), 8, 8, 8, 0, fp.handle, 0, 13, P(1 << 20), None) == -1
+    # the allocation-free variant checks its arguments the same way, first
+    nf = L.median_filter_noalloc
+    assert nf(None, 8, 8, 8, 0, fp.handle, 0, P(4096), None) == -1
+    assert nf(P(4096), 8, 8, 7, 0, fp.handle, 0, P(1 << 20), None) == -1
+    assert nf(P(4096), 8, 8, 8, 7, fp.handle, 0, P(1 << 20), None) == -1
+    assert nf(P(4096), 8, 8, 8, 0, None, 0, P(1 << 20), None) == -1
+    assert nf(P(4096), 8, 8, 8, 0, fp.handle, 0, P(4096 + 16), None) == -2
+    assert nf(P(4096), 8, 0, 8, 0, fp.handle, 0, P(1 << 20), None) == 0
+    assert L.mf_status_string(-6) == b"MF_ERR_SCRATCH_LIMIT"
 
 
 def test_query_plan_geometry():
