@@ -1,15 +1,15 @@
 """Benchmark: exact median filter, 4096x4096 uint16 natural-like image, disc r=32, clamp.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--radius R] [--size S]
-                    [--no-cpu] [--cpu-seconds T] [--legs plain,batched,learned,ranks,windows,stress]
+                    [--no-cpu] [--legs plain,batched,learned,ranks,windows,stress]
                     [--weights PATH] [--copy-check]
 
 One step = one call of the plain filter over the whole image (every step of
 the hot path: tile load, ordinal transform, sliding and omnigram scans,
 reverse map), with the input already resident in device memory.  Prints one
-JSON line.  The CPU-baseline leg times the brute-force oracle on a bounded
-sample of output pixels on the host cores and counts mismatches of the GPU
-output on that sample.
+JSON line.  The CPU-baseline leg runs the brute-force oracle over every
+output pixel of the same image on the host cores (about 20 s on 16 cores),
+timing it and counting mismatches of the GPU output.
 
 Comparison legs in the same line:
   batched  - 64 mixed images (w, h uniform in 128..2048, u8/u16/f32, disc
@@ -57,6 +57,8 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 PLAIN_SOURCES = ("tile_engine.h", "tile_common.h", "mf_internal.h", "median_plain.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles",
                             "mf_plain_kernel_u16_4096x4096_disc_r32_hbm_bytes.md")
+MIX_FILE = os.path.join(ROOT, "profiles",
+                        "mf_plain_kernel_u16_4096x4096_disc_r32_instruction_mix.md")
 
 
 def kernel_sources_hash(plan):
@@ -84,26 +86,88 @@ def measured_traffic(plan):
         return None
 
 
-def work_model(plan, taps, rows, cols, w, h, passes, blocks, seeds, groups):
-    """Algorithmic lane-operations of one filter call:
-    sort 3 ops/element/4-bit pass + 1 op/element for the ordinal image,
-    2*cols compare-accumulates per vertically slid pixel, 2*rows per
-    horizontally slid pixel, 64 membership tests per wave-cooperative scan
-    block, 8 per group tested by one lane, and one histogram update per tap
-    of each seed window."""
+def box_union_px(lo, hi, dy_min, tw, th):
+    """Pixels of the union of the windows centred on a tw x th tile (the
+    rounded rectangle the method must rank): for each box row, the x range
+    covered by the footprint rows that reach it from some tile row."""
+    nrows = len(lo)
+    total = 0
+    for y in range(dy_min, th + dy_min + nrows - 1):     # box row, tile coords
+        dys = [y - ty for ty in range(th) if 0 <= y - ty - dy_min < nrows]
+        if not dys:
+            continue
+        xl = min(lo[dy - dy_min] for dy in dys)
+        xh = max(hi[dy - dy_min] for dy in dys) + tw - 1
+        total += xh - xl + 1
+    return total
+
+
+def band_geometry(plan, w, h):
+    """Output pixels, histogram seeds, 16-column seed moves and horizontally
+    slid pixels of one plain-filter launch, from the plan: bands of
+    ceil(th / (16 * 64 / tw)) rows, each band's first row cut into 16-column
+    chunks (the first from a histogram, the others moved from the previous
+    chunk's seed window), the rest of each chunk slid horizontally."""
     tw, th = plan["tile_w"], plan["tile_h"]
-    T = plan["box_w"] * plan["box_h"]
+    segs = 64 // tw
+    R = -(-th // (16 * segs))
+    npx = seeds = moves = hslid = 0
+    for ty0 in range(0, h, th):
+        rows_in = min(th, h - ty0)
+        bands = -(-rows_in // R)
+        for tx0 in range(0, w, tw):
+            cols_in = min(tw, w - tx0)
+            chunks = -(-cols_in // 16)
+            npx += rows_in * cols_in
+            seeds += bands
+            moves += bands * (chunks - 1)
+            hslid += bands * (cols_in - chunks)
+    first_row = seeds + moves + hslid
+    return dict(px=npx, seeds=seeds, moves=moves, hslid=hslid, vslid=npx - first_row)
+
+
+def work_model(plan, fp, w, h, key_bits, blocks, groups):
+    """Algorithmic lane-operations of one plain-filter launch (the method's own
+    work, not the kernel's instruction count):
+      sort   A * P * 3 per output pixel: ranking the union of the tile's
+             windows (T_union box pixels per tile) with P = key_bits / 8 byte
+             passes of about 3 operations per element;
+      slides 2 * cols compares per vertically slid pixel, 2 * rows per
+             horizontally slid pixel (a 16-column seed move counts as 16
+             horizontal slides);
+      scans  64 omnigram tests per wave-cooperative block, 8 per lane group
+             (both counted by the kernel);
+      seeds  N histogram updates per histogram seed."""
+    tw, th = plan["tile_w"], plan["tile_h"]
+    lo, hi = fp.row_spans()
+    rows = len(lo)
+    cols = fp.dx_max - fp.dx_min + 1
     tiles = -(-w // tw) * -(-h // th)
-    npx = tiles * tw * th                      # computed pixels incl. ragged tiles
-    seed_rows = seeds * tw                     # first rows of bands
-    sort_ops = tiles * T * (3 * passes + 1)
-    slide_ops = (npx - seed_rows) * 2 * cols + (seed_rows - seeds) * 2 * rows
+    t_union = box_union_px(lo, hi, fp.dy_min, tw, th)
+    passes = key_bits // 8
+    g = band_geometry(plan, w, h)
+    sort_ops = tiles * t_union * passes * 3
+    slide_ops = g["vslid"] * 2 * cols + (g["hslid"] + 16 * g["moves"]) * 2 * rows
     scan_ops = 64 * blocks + 8 * groups
-    seed_ops = seeds * taps
+    seed_ops = g["seeds"] * fp.taps
     total = sort_ops + slide_ops + scan_ops + seed_ops
     return dict(total=total, sort=sort_ops, slide=slide_ops, scan=scan_ops, seed=seed_ops,
-                blocks_per_px=blocks / npx, groups_per_px=groups / npx, tiles=tiles,
-                computed_px=npx)
+                t_union=t_union, t_box=plan["box_w"] * plan["box_h"], byte_passes=passes,
+                amplification=t_union / (tw * th), blocks_per_px=blocks / g["px"],
+                groups_per_px=groups / g["px"], tiles=tiles, per_px=total / g["px"], **g)
+
+
+def issued_lane_ops(plan):
+    """VALU lane-instructions per launch (SQ_INSTS_VALU x 64) from the committed
+    counter summary, or None when the kernel or plan changed since."""
+    try:
+        with open(MIX_FILE) as f:
+            kv = dict(l.split(": ", 1) for l in f.read().splitlines() if ": " in l)
+        if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_hash(plan):
+            return None
+        return int(kv["valu_lane_ops_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _time_events(torch, fn, stream, reps):
@@ -429,7 +493,6 @@ def main():
     ap.add_argument("--radius", type=int, default=32)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--legs", default="plain,batched,learned,ranks,windows,stress")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
                                                       "bracket_net.npz"))
@@ -486,21 +549,27 @@ def main():
     cnt = mf.work_counters(-1)
     blocks, seeds, groups = cnt[0], cnt[1], cnt[6]
     nw = max(cnt[5], 1)
-    phase_clk = {"sort": cnt[2] / nw, "rows": cnt[3] / nw, "sweep": cnt[4] / nw}
+    phase_clk = {"sort": cnt[2] / nw, "rows": cnt[3] / nw, "sweep": cnt[4] / nw,
+                 "seeds": cnt[8] / nw, "load": cnt[9] / nw}
     mf.work_counters(0)
-    lo, hi = fp.row_spans()
-    rows = len(lo)
-    cols = fp.dx_max - fp.dx_min + 1
-    wm = work_model(plan, fp.taps, rows, cols, S, S, 4, blocks, seeds, groups)
+    wm = work_model(plan, fp, S, S, 16, blocks, groups)
+    if wm["seeds"] != seeds:
+        print(f"# note: kernel counted {seeds} histogram seeds, plan geometry {wm['seeds']}",
+              file=sys.stderr, flush=True)
     kmean = float(np.mean(kern_ms))
     achieved = wm["total"] / (kmean * 1e-3)
-    traffic = measured_traffic(plan) if (S, r) == (4096, 32) else None
+    full = (S, r) == (4096, 32)
+    traffic = measured_traffic(plan) if full else None
+    issued = issued_lane_ops(plan) if full else None
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                 "unit": "Top/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "hbm_gb_s": traffic / (kmean * 1e-3) / 1e9 if traffic else None,
                 "hbm_frac_of_8tb_s": traffic / (kmean * 1e-3) / 8e12 if traffic else None,
                 "kernel_ms_mean": kmean, "kernel_ms_min": float(np.min(kern_ms)),
+                "algorithmic_lane_ops": wm["total"],
+                "issued_lane_ops": issued,
+                "issued_over_algorithmic": issued / wm["total"] if issued else None,
                 "work_lane_ops": wm, "clocks_per_wave": phase_clk}
     gpu_out = out.cpu().numpy()
 
@@ -536,20 +605,13 @@ def main():
         from oracle import footprints as OF
         ofp = OF.disc(r)
         cores = oracle.default_threads()
-        rng = np.random.default_rng(123)
-        n0 = 20000
-        xs = rng.integers(0, S, n0)
-        ys = rng.integers(0, S, n0)
-        c0 = time.perf_counter()
-        v0 = oracle.filter_points(img_np, ofp, xs, ys, "clamp", nthreads=cores)
-        d0 = time.perf_counter() - c0
-        n1 = int(min(S * S, max(n0, n0 * args.cpu_seconds / max(d0, 1e-3))))
-        xs1 = rng.integers(0, S, n1)
-        ys1 = rng.integers(0, S, n1)
+        # every output pixel of the headline image, on all host cores
         c1 = time.perf_counter()
-        v1 = oracle.filter_points(img_np, ofp, xs1, ys1, "clamp", nthreads=cores)
+        exp = oracle.filter(img_np, ofp, "clamp", nthreads=cores)
         d1 = time.perf_counter() - c1
-        mismatches = int((gpu_out[ys, xs] != v0).sum() + (gpu_out[ys1, xs1] != v1).sum())
+        n1 = S * S
+        mismatches = int((gpu_out != exp).sum())
+        del exp
         # one thread on a 512x512 crop of output pixels, for scaling
         C = min(512, S)
         cy, cx = np.mgrid[0:C, 0:C]
@@ -568,9 +630,9 @@ def main():
         cpu = {"value": n1 / d1 / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
                "cpu_model": model, "one_thread_mpx_s": C * C / d2 / 1e6,
                "one_thread_sample": f"central {C}x{C} crop, {d2:.1f}s",
-               "sample": f"{n1} random output pixels of the same {S}x{S} image, disc r={r} "
+               "sample": f"all {n1} output pixels of the same {S}x{S} image, disc r={r} "
                          f"({fp.taps} taps), brute force gather + nth_element, {d1:.1f}s",
-               "mismatches_vs_gpu": mismatches, "checked_px": n0 + n1 + C * C}
+               "mismatches_vs_gpu": mismatches, "checked_px": n1 + C * C}
 
     line = {
         "metric": "Mpixel/s, r=32 disc uint16 4K, learned/batched vs plain GPU, bit-exact",

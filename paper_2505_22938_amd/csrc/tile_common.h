@@ -75,7 +75,8 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // Elements: `key[i]` holds the sort key in bits [shift0, shift0 + 4*passes);
 // for float keys `pos[i]` is a 16-bit payload sorted alongside.  On entry
 // element i of thread t is element number i*kThreads + t (any order is fine
-// for the first pass); elements numbered >= T are absent.  ITEMS is odd and
+// for the first pass), or t*ITEMS + i with BLOCKED0 (the first pass then
+// keeps that order among equal digits); elements numbered >= T are absent.  ITEMS is odd and
 // ITEMS * kThreads >= T.
 //
 // Output: with PAYLOAD (float keys) the last pass writes the sorted keys to
@@ -85,7 +86,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // values back from the image through the omnigram's locations).  kbuf/pbuf are the exchange buffers of earlier
 // passes; the output arrays may alias them (the last pass reads only
 // registers).
-template <int ITEMS, bool PAYLOAD, bool KEEP_C = true>
+template <int ITEMS, bool PAYLOAD, bool KEEP_C = true, bool BLOCKED0 = false>
 __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
                                                  int T, int shift0, int passes,
                                                  uint32_t* kbuf, uint16_t* pbuf,
@@ -101,7 +102,7 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
     for (int j = 0; j < (ITEMS + 3) / 4; ++j) lr[j] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      const int e = pass == 0 ? i * kThreads + t : t * ITEMS + i;
+      const int e = pass == 0 && !BLOCKED0 ? i * kThreads + t : t * ITEMS + i;
       if (e < T) {
         const uint32_t d = (key[i] >> sh) & 15u;
         const uint32_t s8 = (d & 7u) << 3;
@@ -142,7 +143,7 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
     // 4. scatter
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-      const int e = pass == 0 ? i * kThreads + t : t * ITEMS + i;
+      const int e = pass == 0 && !BLOCKED0 ? i * kThreads + t : t * ITEMS + i;
       if (e < T) {
         const uint32_t d = (key[i] >> sh) & 15u;
         const uint32_t dst = (uint32_t)cnt[d * kThreads + t] + ((lr[i >> 2] >> ((i & 3) * 8)) & 0xffu);
@@ -179,6 +180,65 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
       }
     }
   }
+}
+
+// Counting pass on the low `bits` key bits (at bit `sh`) that does not keep
+// the order of equal digits: bucket sizes by LDS atomics, an exclusive scan
+// over the buckets, then each element claims the next slot of its bucket by
+// a returning atomic on the bucket's running offset.  Ties between equal
+// keys may be broken in any order (they get consecutive ordinals whose
+// reverse-map value is the same), so this may serve as the least
+// significant pass of the LSD sort; the stable passes of block_radix_sort
+// (BLOCKED0) then order the higher bits.  Elements: as block_radix_sort's
+// first pass (striped).  FINAL (8-bit keys, whose low 8 bits are the whole
+// key): the location (low 16 bits of the word) goes straight to omega[slot];
+// otherwise the word goes to kbuf[slot] (and the payload to pbuf[slot]).
+// cnt holds 1 << bits words (bits <= 12); wsum as block_exclusive_scan.
+template <int ITEMS, bool PAYLOAD, bool FINAL>
+__device__ __forceinline__ void bucket_pass(const uint32_t (&key)[ITEMS],
+                                            const uint16_t (&pos)[ITEMS], int T, int sh,
+                                            int bits, uint32_t* kbuf, uint16_t* pbuf,
+                                            uint16_t* omega, uint32_t* cnt, uint32_t* wsum) {
+  const int t = threadIdx.x;
+  const uint32_t mask = (1u << bits) - 1u;
+  const int nb = 1 << bits;
+  for (int b = t; b < nb; b += kThreads) cnt[b] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (i * kThreads + t < T) atomicAdd(&cnt[(key[i] >> sh) & mask], 1u);
+  __syncthreads();
+  // exclusive scan: thread t owns buckets [4t, 4t + 4)
+  {
+    uint32_t c[4] = {0, 0, 0, 0};
+    const bool own = 4 * t < nb;
+    if (own) {
+      const uint4 v = reinterpret_cast<const uint4*>(cnt)[t];
+      c[0] = v.x;
+      c[1] = v.y;
+      c[2] = v.z;
+      c[3] = v.w;
+    }
+    const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+    const uint32_t base = block_exclusive_scan(sum, wsum);
+    if (own)
+      reinterpret_cast<uint4*>(cnt)[t] =
+          make_uint4(base, base + c[0], base + c[0] + c[1], base + c[0] + c[1] + c[2]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    if (i * kThreads + t < T) {
+      const uint32_t dst = atomicAdd(&cnt[(key[i] >> sh) & mask], 1u);
+      if (FINAL) {
+        omega[dst] = (uint16_t)key[i];
+      } else {
+        kbuf[dst] = key[i];
+        if (PAYLOAD) pbuf[dst] = pos[i];
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // Stable LSD radix sort of T elements in global memory, for boxes whose

@@ -5,26 +5,34 @@
 //
 // Tile pipeline, one workgroup of kThreads threads:
 //   load    box = output tile grown by the window extent, boundary-remapped
-//   sort    LSD radix sort of {key, location} -> W[v] (key and location of
-//           ordinal v): the reverse map C and the omnigram (Eq. 4)
+//   sort    radix sort of {key, location} -> the omnigram W[v] (location of
+//           ordinal v; Eq. 4): one counting pass over the low key bits by
+//           LDS atomics (order among equal digits free, since ties may take
+//           their ordinals in any order), then stable 4-bit LSD passes
 //   I       ordinal image, I(loc(v)) = v, 16-bit, row pitch chosen so rows
 //           start in different LDS banks
 //   bands   the tile is cut into bands of `band_rows` rows (the last one
 //           may be shorter) and each wave owns `segs` = 64 / tw bands side
 //           by side (a band is tw <= 64 columns, one lane per column; lanes
 //           past segs * tw and bands past the tile sit out).  Per band:
-//             seed  the first window of the band's first row is solved
-//                   with a coarse histogram of its ordinals, refined by an
-//                   omnigram scan (paper: seeds solved from low-precision
-//                   histograms, then refined);
-//             row   the rest of that row is solved by sliding the window
-//                   right one pixel at a time, the wave testing one footprint
-//                   row per lane for entering and leaving pixels (ballot +
-//                   popcount) against the pivot, then scanning;
+//             seeds the band's first row is cut into chunks of 16 columns;
+//                   the first chunk's window is solved with a coarse
+//                   histogram of its ordinals refined by an omnigram scan
+//                   (paper: seeds solved from low-precision histograms, then
+//                   refined), each later chunk's by moving the previous
+//                   chunk's window 16 columns right;
+//             row   the four 16-lane rows of the wave take one chunk each
+//                   and slide their windows right one pixel at a time in
+//                   lockstep (paper: short horizontal slides from many
+//                   seeds), counting entering and leaving pixels against
+//                   the pivot across the row's lanes and refining by a
+//                   row-wide omnigram scan;
 //             sweep every lane then slides its window down the band: count
 //                   += #entering < pivot - #leaving < pivot over the window's
 //                   columns (adjacent lanes read adjacent pixels), then each
-//                   lane's window is refined by a wave-cooperative scan.
+//                   lane walks the omnigram for its window's new median;
+//                   lanes with long walks are finished four at a time by
+//                   16-lane rows.
 //   The pivot is the previous window's median ordinal m, whose count in the
 //   previous window is exactly the rank k, so no separate count is stored
 //   (the paper notes any pivot with a known count works).
@@ -335,17 +343,27 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
   hist[lane * 2] = 0;
   hist[lane * 2 + 1] = 0;
   wave_lds_sync();
+  // one footprint row per lane; eight ordinals read before their eight
+  // histogram updates, so the reads overlap instead of each waiting behind
+  // the previous update
+  constexpr int kBatch = 8;
   for (int i = lane; i < f.nrows; i += 64) {
     const short2 s = rsp[i];
     const int row = (cy + f.dy_min + i) * a.pitch + cx;
-    for (int x = s.x; x <= s.y; ++x) {
-      const uint32_t iv = I[row + x];
-      if (BR) {
-        zeros += iv == 0;
-        if (iv == 0 || iv == 0xffffu) continue;
+    for (int x0 = s.x; x0 <= s.y; x0 += kBatch) {
+      uint32_t iv[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) iv[j] = I[row + min(x0 + j, (int)s.y)];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        if (x0 + j > s.y) break;
+        if (BR) {
+          zeros += iv[j] == 0;
+          if (iv[j] == 0 || iv[j] == 0xffffu) continue;
+        }
+        const uint32_t b = iv[j] >> hshift;
+        atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
       }
-      const uint32_t b = iv >> hshift;
-      atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
     }
   }
   if (BR)
@@ -386,39 +404,159 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
   return scan_select<KT, SHAPE, OM_LDS>(p, sbase, k, cx, cy, T, a, f, om, rsp, blocks, c_end);
 }
 
-// Count change when the window centred at box (cx, cy) moves right by one
-// pixel, against pivot p: lanes take footprint rows lane and lane + 64 (and
-// further rounds of 128 rows for taller windows); hrow[i] = (entering
-// offset, leaving offset) of row i.
-template <typename D>
-__device__ __forceinline__ int hstep_delta(int cx, int cy, int p, const D& a, const Fp& f,
-                                           const uint16_t* I, const int2* hrow,
-                                           const int4& own) {
-  const int lane = threadIdx.x & 63;
-  const int base = cy * a.pitch + cx;
-  // rows lane and lane + 64: offsets held in registers (own); a row beyond
-  // the footprint reads the same entry twice and cancels
-  int delta = __popcll(wave_ballot(I[base + own.x] < p)) -
-              __popcll(wave_ballot(I[base + own.y] < p)) +
-              __popcll(wave_ballot(I[base + own.z] < p)) -
-              __popcll(wave_ballot(I[base + own.w] < p));
-  for (int i0 = 128; i0 < f.nrows; i0 += 128) {
-    const int i1 = i0 + lane, i2 = i0 + 64 + lane;
-    bool e1 = false, l1 = false, e2 = false, l2 = false;
-    if (i1 < f.nrows) {
-      const int2 o = hrow[i1];
-      e1 = I[base + o.x] < p;
-      l1 = I[base + o.y] < p;
+// 16-lane rows of a wave (DPP rows).  Call with every lane of the wave
+// active; lanes that should not contribute pass 0.
+// Sum over the lane's row, in every lane of the row.
+__device__ __forceinline__ int row_sum16(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, false);   // row_ror:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xf, 0xf, false);   // row_ror:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x122, 0xf, 0xf, false);   // row_ror:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x121, 0xf, 0xf, false);   // row_ror:1
+  return x;
+}
+// Largest value over the lane's row, in every lane of the row.
+__device__ __forceinline__ int row_max16(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x122, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x121, 0xf, 0xf, false));
+  return x;
+}
+// Inclusive prefix sum along the lane's row (row_shr with zero fill).
+__device__ __forceinline__ int row_incl_scan16(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);    // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);    // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);    // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);    // row_shr:8
+  return x;
+}
+
+// Index (0..7) of the n-th set bit (from bit 0) of an 8-bit mask that has
+// more than n set bits: halving by nibble, pair and bit.
+__device__ __forceinline__ int nth_bit8(uint32_t x, int n) {
+  int jsel = 0;
+  int cn = __builtin_popcount(x & 15u);
+  if (n >= cn) { n -= cn; jsel += 4; x >>= 4; }
+  cn = __builtin_popcount(x & 3u);
+  if (n >= cn) { n -= cn; jsel += 2; x >>= 2; }
+  if (n >= (int)(x & 1u)) jsel += 1;
+  return jsel;
+}
+
+// Rank selection for one window per 16-lane row, the row's lanes
+// cooperating (row-uniform arguments; `act` false: the row has no window).
+// Same contract as scan_select: pivot p with c window members below it;
+// returns the member ordinal with exactly k members below it.  Each step of
+// the loop tests 128 ordinals of the omnigram, eight per lane (one 16-byte
+// read), upwards from p (c <= k) or downwards from p - 1, and a prefix sum
+// of the lanes' member counts along the row locates the one holding rank k
+// (paper, Eq. 2/3 and the block-wise refinement of "Implementation", with a
+// block of 128).  Ordinals at or past T (going up) or below 0 (going down)
+// are never members: -1 is returned with c_end = the number of members
+// below T (up) or below ordinal 0 (down), as scan_core does.
+template <int SHAPE>
+__device__ __forceinline__ int row_select(bool act, int p, int c, int k, uint32_t cxy, int T,
+                                          const Fp& f, const uint16_t* om, const short2* rsp,
+                                          int& groups, int& c_end) {
+  const int j = threadIdx.x & 15;
+  const bool up = c <= k;
+  int need = up ? k - c : c - 1 - k;   // members to pass before the one sought
+  int q = up ? (p & ~7) : ((p - 1) & ~7);
+  bool done = !act;
+  int res = -1;
+  const int cap = (T >> 7) + 2;
+  for (int it = 0; it < cap; ++it) {
+    if (wave_ballot(!done) == 0) break;
+    const int qj = up ? q + 8 * j : q - 8 * j;
+    const bool valid = !done && (up ? qj < T : qj >= 0);
+    uint32_t bits = 0;
+    if (valid) {
+      const uint4 g = *reinterpret_cast<const uint4*>(om + qj);
+      bits = group_mask<SHAPE>(g, cxy, f, rsp);
+      if (it == 0 && j == 0) bits &= up ? (0xffu << (p - q)) : ((1u << (p - q)) - 1u);
+      ++groups;
     }
-    if (i2 < f.nrows) {
-      const int2 o = hrow[i2];
-      e2 = I[base + o.x] < p;
-      l2 = I[base + o.y] < p;
+    const int pc = __builtin_popcount(bits);
+    const int incl = row_incl_scan16(pc);
+    const int tot = __shfl(incl, (int)(threadIdx.x | 15u), 64);
+    const int before = incl - pc;
+    int cand = -1;
+    if (valid && before <= need && need < incl) {
+      const int n = need - before;
+      cand = up ? qj + nth_bit8(bits, n) : qj + nth_bit8(bits, pc - 1 - n);
     }
-    delta += __popcll(wave_ballot(e1)) + __popcll(wave_ballot(e2)) -
-             __popcll(wave_ballot(l1)) - __popcll(wave_ballot(l2));
+    cand = row_max16(cand);
+    if (!done) {
+      if (need < tot) {
+        res = cand;
+        done = true;
+      } else {
+        need -= tot;
+        q += up ? 128 : -128;
+        if (up ? q >= T : q < 0) {
+          done = true;
+          c_end = up ? k - need : k + 1 + need;
+        }
+      }
+    }
   }
-  return delta;
+  return res;
+}
+
+// Rank selection for one window by the whole wave (wave-uniform
+// arguments), 512 ordinals per step, eight per lane; otherwise as
+// row_select.  Used where the member sought may lie far from the pivot.
+template <int SHAPE>
+__device__ __forceinline__ int wave_select(int p, int c, int k, uint32_t cxy, int T, const Fp& f,
+                                           const uint16_t* om, const short2* rsp, int& groups,
+                                           int& c_end) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const bool up = c <= k;
+  int need = up ? k - c : c - 1 - k;
+  int q = up ? (p & ~7) : ((p - 1) & ~7);
+  const int cap = (T >> 9) + 2;
+  for (int it = 0; it < cap; ++it) {
+    const int ql = up ? q + 8 * lane : q - 8 * lane;
+    const bool valid = up ? ql < T : ql >= 0;
+    uint32_t bits = 0;
+    if (valid) {
+      const uint4 gv = *reinterpret_cast<const uint4*>(om + ql);
+      bits = group_mask<SHAPE>(gv, cxy, f, rsp);
+      if (it == 0 && lane == 0) bits &= up ? (0xffu << (p - q)) : ((1u << (p - q)) - 1u);
+      ++groups;
+    }
+    const int pc = __builtin_popcount(bits);
+    int incl = row_incl_scan16(pc);
+    const int t0 = __builtin_amdgcn_readlane(incl, 15), t1 = __builtin_amdgcn_readlane(incl, 31);
+    const int t2 = __builtin_amdgcn_readlane(incl, 47), t3 = __builtin_amdgcn_readlane(incl, 63);
+    incl += (g >= 1 ? t0 : 0) + (g >= 2 ? t1 : 0) + (g >= 3 ? t2 : 0);
+    const int tot = t0 + t1 + t2 + t3;
+    if (need < tot) {
+      const int before = incl - pc;
+      const bool hit = valid && before <= need && need < incl;
+      const uint64_t hm = wave_ballot(hit);
+      int cand = 0;
+      if (hit) {
+        const int n = need - before;
+        cand = up ? ql + nth_bit8(bits, n) : ql + nth_bit8(bits, pc - 1 - n);
+      }
+      return __builtin_amdgcn_readlane(cand, __ffsll((unsigned long long)hm) - 1);
+    }
+    need -= tot;
+    q += up ? 512 : -512;
+    if (up ? q >= T : q < 0) {
+      c_end = up ? k - need : k + 1 + need;
+      return -1;
+    }
+  }
+  return -1;
+}
+
+// Sum over the whole wave, in every lane (all lanes active).
+__device__ __forceinline__ int wave_sum(int x) {
+  x = row_sum16(x);
+  return __builtin_amdgcn_readlane(x, 0) + __builtin_amdgcn_readlane(x, 16) +
+         __builtin_amdgcn_readlane(x, 32) + __builtin_amdgcn_readlane(x, 48);
 }
 
 // Reverse map (paper, "Method Summary" step 7): the output is C[m], the
@@ -762,14 +900,25 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       }
     }
     clk_load = a.counters ? (long long)clock64() : 0;
-    // 2. ordinal transform
-    const int passes = KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8;
-    if (KT == KEY_F32)
-      block_radix_sort<IMAX, true, false>(key, pos, T, 0, passes, kbuf, pbuf, om, nullptr,
-                                          nullptr, cnt, wsum);
-    else
-      block_radix_sort<IMAX, false, false>(key, pos, T, 16, passes, kbuf, pbuf, om, nullptr,
-                                           nullptr, cnt, wsum);
+    // 2. ordinal transform: one bucket pass over the low 8 (8-bit keys) or
+    // 12 key bits, then stable 4-bit passes over the rest (one for 16-bit
+    // keys, five for float keys)
+    uint32_t* bcnt = reinterpret_cast<uint32_t*>(cnt);
+    if constexpr (KT == KEY_U8) {
+      bucket_pass<IMAX, false, true>(key, pos, T, 16, 8, kbuf, pbuf, om, bcnt, wsum);
+    } else {
+      constexpr bool PL = KT == KEY_F32;
+      const int sh = PL ? 0 : 16;
+      bucket_pass<IMAX, PL, false>(key, pos, T, sh, 12, kbuf, pbuf, om, bcnt, wsum);
+#pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = t * IMAX + i;
+        key[i] = e < T ? kbuf[e] : 0u;
+        if (PL) pos[i] = e < T ? pbuf[e] : (uint16_t)0;
+      }
+      block_radix_sort<IMAX, PL, false, true>(key, pos, T, sh + 12, PL ? 5 : 1, kbuf, pbuf, om,
+                                              nullptr, nullptr, cnt, wsum);
+    }
   } else {
     // load the box straight into global scratch as (key << 16 | location)
     // words: 32-bit for 8/16-bit keys, 64-bit for float keys
@@ -839,21 +988,6 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   const int row0 = band * R;                 // first output row of this lane's band
   const int cxl = col - a.dx_min;            // lane's window centre, box coords
   const int cols_in = min(tw, a.w - tx0);
-  // this lane's rows of hrow (lane, lane + 64); rows beyond the footprint
-  // read one entry twice and cancel
-  auto own_rows = [&]() {
-    int4 o = make_int4(0, 0, 0, 0);
-    if (lane < f.nrows) {
-      o.x = hrow[lane].x;
-      o.y = hrow[lane].y;
-    }
-    if (lane + 64 < f.nrows) {
-      o.z = hrow[lane + 64].x;
-      o.w = hrow[lane + 64].y;
-    }
-    return o;
-  };
-  int4 hown = own_rows();
   const int nq = GEN ? a.nq : 1;
   for (int q = 0; q < nq; ++q) {
   if (mfp && q > 0) {
@@ -864,7 +998,6 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     fcols = pq.ncols;
     build_tables(pq.spans, pq.nrows, pq.ncols, pq.dx_min, pq.dy_min);
     __syncthreads();
-    hown = own_rows();
   }
   void* const outq = GEN ? a.outs[q] : a.out;
   const int k0 = GEN ? a.ranks[q] : a.rank;
@@ -878,51 +1011,138 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   // the bracket.
   int m = 0, vp = 0, vc = k0, miss = 0;
 
-  // 4a. seed + first row of each band, one segment at a time.  Windows
-  // outside the image are not computed: bands starting below it are
-  // skipped and the walk stops at the last column inside it.
-  for (int s = 0; s < segs; ++s) {
-    const int brow = (wid * segs + s) * R;
-    if (brow >= a.th || ty0 + brow >= a.h) break;   // band below the tile or the image
-    const int cy = brow - a.dy_min;
-    // ranks of this row's pixels, lane c holding column c (general form)
-    const int krow = rank_at<GEN>(a, q, k0, tx0 + lane, ty0 + brow, lane < cols_in);
-    const int kseed = GEN ? __builtin_amdgcn_readfirstlane(krow) : k0;
-    int ep = 0, ec = 0;
-    const long long cs0 = a.counters ? (long long)clock64() : 0;
-    int ms = seed_solve<KT, SHAPE, BR, !GS>(0 - a.dx_min, cy, Tv, hshift, kseed, a, f, om, I, hist, rsp,
-                                       blocks, ep, ec);
-    if (a.counters) seed_clk += (long long)clock64() - cs0;
-    ++seeds;
-    int hp = ms, hc = kseed;   // wave-uniform pivot and count
-    if (BR && ms < 0) {
-      hp = ep;
-      hc = ec;
-    }
-    m = set_lane(ms, s * tw, m);
-    vp = set_lane(hp, s * tw, vp);
-    vc = set_lane(hc, s * tw, vc);
-    if (BR) miss = set_lane(ms < 0, s * tw, miss);
-    for (int c = 1; c < cols_in; ++c) {
-      const int kc = GEN ? __builtin_amdgcn_readlane(krow, c) : k0;
-      const int cxp = c - 1 - a.dx_min;
-      const uint32_t pre_up = om[min(hp + lane, Tv - 1)];
-      const uint32_t pre_dn = om[max(hp - 64 + lane, 0)];
-      const int cnt_new = hc + hstep_delta(cxp, cy, hp, a, f, I, hrow, hown);
-      int c_end = 0;
-      ms = scan_core<SHAPE, !GS>(hp, cnt_new, kc, (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, a,
-                            f, om, rsp, blocks, pre_up, pre_dn, c_end);
-      if (!BR || ms >= 0) {
-        hp = ms;
-        hc = kc;
-      } else {
-        hp = cnt_new <= kc ? Tv : 1;
-        hc = c_end;
+  // 4a. first rows of the wave's bands (paper, "GPU": seeds solved from
+  // histograms, then short horizontal slides from each seed).  The columns
+  // of each band's first row are cut into chunks of at most 16, each
+  // starting from its own seed window; the four 16-lane rows of the wave
+  // take one chunk each and slide their windows right in lockstep: lane j
+  // of a row counts the entering and leaving pixels of footprint rows j,
+  // j + 16, ... against the row's pivot, a row-wide sum gives the count,
+  // and row_select refines it.  Windows outside the image are not
+  // computed: chunks of bands below the tile or the image are skipped and
+  // a chunk ends at the last column inside the image.  Results reach the
+  // sweep's lanes (lane = seg * tw + col) by a lane shuffle per round.
+  {
+    const int g = lane >> 4, j = lane & 15;
+    const int nchb = (cols_in + 15) >> 4;       // chunks per band row
+    const int nch = segs * nchb;
+    int lp = 0, lc = 0;   // pivot and count of the last seed solved
+    for (int r0 = 0; r0 < nch; r0 += 4) {
+      // this row's chunk: band s, first column c0, len columns
+      const int ch = r0 + g;
+      const int sb = ch / nchb, c0 = (ch - sb * nchb) << 4;
+      const int brow = (wid * segs + sb) * R;
+      const bool ok = ch < nch && brow < a.th && ty0 + brow < a.h;
+      const int len = ok ? min(16, cols_in - c0) : 0;
+      const int cy = brow - a.dy_min;
+      // ranks of the chunk's pixels, lane j holding column c0 + j
+      const int krow = rank_at<GEN>(a, q, k0, tx0 + c0 + j, ty0 + brow, ok && j < len);
+      int hp = 0, hc = 0;                       // the row's pivot and count
+      int m_l = 0, vp_l = 0, vc_l = k0, miss_l = 0;   // results, lane j = column c0 + j
+      // seeds, one wave-wide solve per chunk of the round: a band's first
+      // chunk from a histogram, each later chunk by moving the previous
+      // chunk's seed window 16 columns right (entering and leaving pixels
+      // of every footprint row counted against its pivot, then a wave-wide
+      // omnigram scan)
+      for (int gg = 0; gg < 4; ++gg) {
+        const int chg = r0 + gg;
+        if (chg >= nch) break;
+        const int sg = chg / nchb, c0g = (chg - sg * nchb) << 4;
+        const int browg = (wid * segs + sg) * R;
+        if (browg >= a.th || ty0 + browg >= a.h) continue;
+        const int kseed = GEN ? __builtin_amdgcn_readlane(krow, 16 * gg) : k0;
+        const int cyg = browg - a.dy_min;
+        const long long cs0 = a.counters ? (long long)clock64() : 0;
+        int ms, sp, sc;
+        if (c0g == 0) {
+          int ep = 0, ec = 0;
+          ms = seed_solve<KT, SHAPE, BR, !GS>(0 - a.dx_min, cyg, Tv, hshift, kseed, a, f, om, I,
+                                              hist, rsp, blocks, ep, ec);
+          ++seeds;
+          sp = (BR && ms < 0) ? ep : ms;
+          sc = (BR && ms < 0) ? ec : kseed;
+        } else {
+          const int cx0 = c0g - 16 - a.dx_min;   // previous seed's centre
+          const int jb = cyg * a.pitch + cx0;
+          int d = 0;
+          for (int e = lane; e < (f.nrows << 4); e += 64) {
+            const int2 o = hrow[e >> 4];
+            const int tt = e & 15;
+            d += (int)(I[jb + o.x + tt] < (uint32_t)lp) - (int)(I[jb + o.y + tt] < (uint32_t)lp);
+          }
+          const int cnt = lc + wave_sum(d);
+          int c_end = 0;
+          ms = wave_select<SHAPE>(lp, cnt, kseed, (uint32_t)(cx0 + 16) | ((uint32_t)cyg << 16),
+                                  Tv, f, om, rsp, groups, c_end);
+          sp = (!BR || ms >= 0) ? ms : (cnt <= kseed ? Tv : 1);
+          sc = (!BR || ms >= 0) ? kseed : c_end;
+        }
+        lp = sp;
+        lc = sc;
+        if (a.counters) seed_clk += (long long)clock64() - cs0;
+        if (g == gg) {
+          hp = sp;
+          hc = sc;
+        }
+        if (lane == 16 * gg) {
+          m_l = ms;
+          vp_l = sp;
+          vc_l = sc;
+          miss_l = ms < 0;
+        }
       }
-      m = set_lane(ms, s * tw + c, m);
-      vp = set_lane(hp, s * tw + c, vp);
-      vc = set_lane(hc, s * tw + c, vc);
-      if (BR) miss = set_lane(ms < 0, s * tw + c, miss);
+      // horizontal slides, all rows in lockstep; the lane's first five
+      // footprint rows' offsets stay in registers
+
+      const int steps = __builtin_amdgcn_readfirstlane(
+          max(max(__shfl(len, 0, 64), __shfl(len, 16, 64)),
+              max(__shfl(len, 32, 64), __shfl(len, 48, 64))));
+      for (int t = 1; t < steps; ++t) {
+        const bool act = t < len;
+        const int kc = GEN ? __shfl(krow, (int)((threadIdx.x & ~15u) | (unsigned)t), 64) : k0;
+        const int cxp = c0 + t - 1 - a.dx_min;   // previous centre, box x
+        const int base = cy * a.pitch + cxp;
+        int d = 0;
+        if (act) {
+          // rows beyond the footprint read the centre twice and cancel
+          for (int i = j; i < f.nrows; i += 16) {
+            const int2 o = hrow[i];
+            d += (int)(I[base + o.x] < (uint32_t)hp) - (int)(I[base + o.y] < (uint32_t)hp);
+          }
+        }
+        const int cnt = hc + row_sum16(d);
+        int c_end = 0;
+        const int ms = row_select<SHAPE>(act, hp, cnt, kc,
+                                         (uint32_t)(cxp + 1) | ((uint32_t)cy << 16), Tv, f, om,
+                                         rsp, groups, c_end);
+        if (act) {
+          if (!BR || ms >= 0) {
+            hp = ms;
+            hc = kc;
+          } else {
+            hp = cnt <= kc ? Tv : 1;
+            hc = c_end;
+          }
+          if (j == t) {
+            m_l = ms;
+            vp_l = hp;
+            vc_l = hc;
+            miss_l = ms < 0;
+          }
+        }
+      }
+      // hand this round's columns to the sweep lanes
+      const int chu = seg * nchb + (col >> 4);
+      const bool mine = lane < segs * tw && col < cols_in && chu >= r0 && chu < r0 + 4;
+      const int src = mine ? (((chu - r0) << 4) | (col & 15)) : 0;
+      const int mv = __shfl(m_l, src, 64), pv = __shfl(vp_l, src, 64);
+      const int cv = __shfl(vc_l, src, 64), xv = __shfl(miss_l, src, 64);
+      if (mine) {
+        m = mv;
+        vp = pv;
+        vc = cv;
+        miss = xv;
+      }
     }
   }
   if (a.counters) seed_taps = seeds;  // taps per seed added on the host
@@ -965,21 +1185,36 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
         if (pl <= 0) pl = 1;
       }
     }
+    // lanes still walking: four at a time, each finished by one 16-lane row
+    // of the wave (row_select, 128 ordinals per step)
     uint64_t left = wave_ballot(lane_active && mnew < 0 && !esc);
     while (left) {
-      const int L = __ffsll((unsigned long long)left) - 1;
-      left &= left - 1;
-      const int cxyL = __builtin_amdgcn_readlane((int)cxy, L);
-      const int plL = __builtin_amdgcn_readlane(pl, L), clL = __builtin_amdgcn_readlane(cl, L);
-      const int kL = GEN ? __builtin_amdgcn_readlane(kl, L) : k0;
+      int Ls[4];
+#pragma unroll
+      for (int gi = 0; gi < 4; ++gi) {
+        Ls[gi] = left ? __ffsll((unsigned long long)left) - 1 : -1;
+        left &= left - 1;
+      }
+      const int rg = lane >> 4;
+      const int Lg = rg == 0 ? Ls[0] : rg == 1 ? Ls[1] : rg == 2 ? Ls[2] : Ls[3];
+      const int Lsrc = max(Lg, 0);
+      const int plg = __shfl(pl, Lsrc, 64), clg = __shfl(cl, Lsrc, 64);
+      const int kg = GEN ? __shfl(kl, Lsrc, 64) : k0;
+      const uint32_t cxyg = (uint32_t)__shfl((int)cxy, Lsrc, 64);
       int c_end = 0;
-      const int mL = scan_select<KT, SHAPE, !GS>(plL, clL, kL, cxyL & 0xffff, cxyL >> 16, Tv, a, f,
-                                            om, rsp, blocks, c_end);
-      mnew = set_lane(mL, L, mnew);
-      if (BR && mL < 0) {
-        pl = set_lane(clL <= kL ? Tv : 1, L, pl);
-        cl = set_lane(c_end, L, cl);
-        esc = set_lane(1, L, esc);
+      const int mr = row_select<SHAPE>(Lg >= 0, plg, clg, kg, cxyg, Tv, f, om, rsp, groups, c_end);
+      int slot = -1;
+#pragma unroll
+      for (int gi = 0; gi < 4; ++gi) slot = lane == Ls[gi] ? gi : slot;
+      const int src = slot >= 0 ? slot << 4 : 0;
+      const int mb = __shfl(mr, src, 64), ceb = __shfl(c_end, src, 64);
+      if (slot >= 0) {
+        mnew = mb;
+        if (BR && mb < 0) {
+          pl = cl <= kl ? Tv : 1;
+          cl = ceb;
+          esc = 1;
+        }
       }
     }
     if (lane_active) {
