@@ -243,10 +243,12 @@ __device__ __forceinline__ void bucket_pass(const uint32_t (&key)[ITEMS],
 
 // Stable LSD radix sort of T elements in global memory, for boxes whose
 // sort exchange does not fit in LDS.  Elements are words (key << 16 |
-// location), 32-bit for 8/16-bit keys and 64-bit for 32-bit keys; the key
-// occupies bits [16, 16 + 4*passes).  Each pass ping-pongs between x0 and
-// x1; `passes` is even, so the final pass reads x1 and writes the x0 region:
-// locations to omega[] and keys to crev16[] (16-bit keys) or crev32[].
+// location), 32-bit for 8/16-bit keys and 64-bit for 32-bit keys; the
+// passes sort bits [shift0, shift0 + 4*passes).  Pass p reads xa (p even)
+// or xb (p odd) and writes the other; the last pass writes neither but
+// splits each word into its location (omega[]) and key (crev16[] for
+// 16-bit keys, else crev32[]), which may alias the buffer that pass does
+// not read.
 //
 // Element e is visited by thread e % kThreads in chunk e / kThreads, so
 // every load is coalesced.  The stable rank of an element is the scanned
@@ -262,7 +264,7 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 template <typename W>
-__device__ __forceinline__ void global_radix_sort(W* x0, W* x1, int T, int passes,
+__device__ __forceinline__ void global_radix_sort(W* xa, W* xb, int T, int shift0, int passes,
                                                   uint16_t* omega, uint16_t* crev16,
                                                   uint32_t* crev32, uint16_t* cnt,
                                                   uint32_t* wsum) {
@@ -270,9 +272,9 @@ __device__ __forceinline__ void global_radix_sort(W* x0, W* x1, int T, int passe
   const int nchunks = (T + kThreads - 1) / kThreads;
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int pass = 0; pass < passes; ++pass) {
-    const W* src = (pass & 1) ? x1 : x0;
-    W* dst = (pass & 1) ? x0 : x1;
-    const int sh = 16 + 4 * pass;
+    const W* src = (pass & 1) ? xb : xa;
+    W* dst = (pass & 1) ? xa : xb;
+    const int sh = shift0 + 4 * pass;
     const bool last = pass + 1 == passes;
     // zero the counters (16 entries per thread)
     {
@@ -332,6 +334,44 @@ __device__ __forceinline__ void global_radix_sort(W* x0, W* x1, int T, int passe
     }
     __syncthreads();
   }
+}
+
+// Global-memory form of bucket_pass: one counting pass over `bits` (<= 12)
+// key bits at bit `sh` of the words in src, without keeping the order of
+// equal digits (LDS atomics count the buckets and then hand out slots), the
+// words scattered to dst.  cnt: 1 << bits LDS words.
+template <typename W>
+__device__ __forceinline__ void global_bucket_pass(const W* src, W* dst, int T, int sh, int bits,
+                                                   uint32_t* cnt, uint32_t* wsum) {
+  const int t = threadIdx.x;
+  const uint32_t mask = (1u << bits) - 1u;
+  const int nb = 1 << bits;
+  for (int b = t; b < nb; b += kThreads) cnt[b] = 0;
+  __syncthreads();
+  for (int e = t; e < T; e += kThreads) atomicAdd(&cnt[(uint32_t)(src[e] >> sh) & mask], 1u);
+  __syncthreads();
+  {
+    uint32_t c[4] = {0, 0, 0, 0};
+    const bool own = 4 * t < nb;
+    if (own) {
+      const uint4 v = reinterpret_cast<const uint4*>(cnt)[t];
+      c[0] = v.x;
+      c[1] = v.y;
+      c[2] = v.z;
+      c[3] = v.w;
+    }
+    const uint32_t sum = c[0] + c[1] + c[2] + c[3];
+    const uint32_t base = block_exclusive_scan(sum, wsum);
+    if (own)
+      reinterpret_cast<uint4*>(cnt)[t] =
+          make_uint4(base, base + c[0], base + c[0] + c[1], base + c[0] + c[1] + c[2]);
+  }
+  __syncthreads();
+  for (int e = t; e < T; e += kThreads) {
+    const W v = src[e];
+    dst[atomicAdd(&cnt[(uint32_t)(v >> sh) & mask], 1u)] = v;
+  }
+  __syncthreads();
 }
 
 }  // namespace mf

@@ -937,9 +937,24 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       x0[e] = (kk << 16) | (W)((ly << 8) | lx);
     }
     __syncthreads();
-    global_radix_sort<W>(x0, x1, T, KT == KEY_U8 ? 2 : KT == KEY_U16 ? 4 : 8, om,
-                         KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
-                         wsum);
+    // a counting pass over the low 8 (8-bit keys) or 12 key bits that does
+    // not keep the order of ties, then stable 4-bit passes over the rest
+    // (none, one for 16-bit keys, five for float keys); the last pass
+    // splits the words into the omnigram and the reverse map
+    uint32_t* bcnt = reinterpret_cast<uint32_t*>(cnt);
+    global_bucket_pass<W>(x0, x1, T, 16, KT == KEY_U8 ? 8 : 12, bcnt, wsum);
+    if constexpr (KT == KEY_U8) {
+      for (int e = t; e < T; e += kThreads) {
+        const W v = x1[e];
+        om[e] = (uint16_t)v;
+        crev[e] = (uint16_t)(v >> 16);
+      }
+      __syncthreads();
+    } else {
+      global_radix_sort<W>(x1, x0, T, 28, KT == KEY_U16 ? 1 : 5, om,
+                           KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
+                           wsum);
+    }
   }
   if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)
