@@ -178,16 +178,19 @@ int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   const int TP = round_up(T, 8) + 16;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
   const int hb = kWaves * 128 * 4;
-  const int B = std::max(kCounterBytes, ib + hb);
-  // slot: x0 and x1, TP words each (32-bit words for 8/16-bit keys, 64-bit
-  // for float keys); after the sort x0 holds omega (u16) + C16, or C32 +
-  // omega
+  const int B0 = std::max(kCounterBytes, ib + hb);
+  // slot: float keys: x0 and x1, TP 64-bit words each, x0 holding C32 +
+  // omega after the sort; 8/16-bit keys: omega (u16) + C16 only
   const int wb = dtype == MF_F32 ? 8 : 4;
+  // region B also holds the sort's packed 16-bit key counters (2^16 of
+  // them for 16-bit and float keys, 2^8 for 8-bit keys)
+  const int B = std::max(B0, dtype == MF_U8 ? 512 : 131072);
   d->off_p = 4 * TP;
   d->off_C = dtype == MF_F32 ? 0 : 2 * TP;
+  // (8/16-bit keys need only the omnigram and C16, 4 * TP bytes)
   d->off_x1 = wb * TP;
   d->off_lr = 0;
-  d->slot_bytes = round_up(2 * wb * TP, 256);
+  d->slot_bytes = round_up(dtype == MF_F32 ? 2 * wb * TP : 4 * TP, 256);
   d->ipt = (T + kThreads - 1) / kThreads;
   d->off_B = 0;
   d->off_I = 0;

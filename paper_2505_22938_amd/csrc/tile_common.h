@@ -374,4 +374,27 @@ __device__ __forceinline__ void global_bucket_pass(const W* src, W* dst, int T, 
   __syncthreads();
 }
 
+// Exclusive scan, in place, over the 2 * nw 16-bit counters packed two per
+// word in w (counter 2i in the low half of word i); the totals stay below
+// 65536.  Thread t scans a contiguous run of words.  Contains barriers.
+__device__ __forceinline__ void packed_exclusive_scan(uint32_t* w, int nw, uint32_t* wsum) {
+  const int t = threadIdx.x;
+  const int per = (nw + kThreads - 1) / kThreads;
+  const int w0 = t * per;
+  uint32_t sum = 0;
+  for (int i = 0; i < per; ++i)
+    if (w0 + i < nw) {
+      const uint32_t v = w[w0 + i];
+      sum += (v & 0xffffu) + (v >> 16);
+    }
+  uint32_t base = block_exclusive_scan(sum, wsum);
+  for (int i = 0; i < per; ++i)
+    if (w0 + i < nw) {
+      const uint32_t v = w[w0 + i];
+      const uint32_t lo = v & 0xffffu;
+      w[w0 + i] = base | ((base + lo) << 16);
+      base += lo + (v >> 16);
+    }
+}
+
 }  // namespace mf

@@ -920,41 +920,56 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
                                               nullptr, nullptr, cnt, wsum);
     }
   } else {
-    // load the box straight into global scratch as (key << 16 | location)
-    // words: 32-bit for 8/16-bit keys, 64-bit for float keys
+    // One counting pass over the low 16 bits of the key (8-bit keys: all
+    // 8): box pixels are counted per key value straight from the image by
+    // LDS atomics on packed 16-bit counters, the counters are scanned, and
+    // each pixel is read again and claims the next slot of its key value.
+    // Ties take their slots in any order, which the ordinal transform
+    // allows, so 8/16-bit keys are fully sorted: the omnigram and the
+    // reverse map are written directly.  Float keys go to global scratch
+    // as (key << 16 | location) words for four stable 4-bit passes over
+    // the high 16 bits.
     using W = typename std::conditional<KT == KEY_F32, uint64_t, uint32_t>::type;
     W* x0 = reinterpret_cast<W*>(gslot);
     W* x1 = reinterpret_cast<W*>(gslot + a.off_x1);
-    for (int e = t; e < T; e += kThreads) {
+    uint32_t* pcnt = reinterpret_cast<uint32_t*>(cnt);
+    constexpr int KB = KT == KEY_U8 ? 8 : 16;
+    constexpr int NW = 1 << (KB - 1);   // counter words, two counters each
+    auto box_key = [&](int e, uint32_t& loc) -> uint32_t {
       const int ly = e / a.bw, lx = e - ly * a.bw;
       const int gx = remap(gx0 + lx, a.w, a.boundary);
       const int gy = remap(gy0 + ly, a.h, a.boundary);
       const long long off = (long long)gy * a.stride + gx;
-      W kk;
-      if (KT == KEY_U8) kk = static_cast<const uint8_t*>(a.img)[off];
-      else if (KT == KEY_U16) kk = static_cast<const uint16_t*>(a.img)[off];
-      else kk = (W)f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
-      x0[e] = (kk << 16) | (W)((ly << 8) | lx);
+      loc = (uint32_t)((ly << 8) | lx);
+      if (KT == KEY_U8) return static_cast<const uint8_t*>(a.img)[off];
+      if (KT == KEY_U16) return static_cast<const uint16_t*>(a.img)[off];
+      return f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+    };
+    for (int b = t; b < NW; b += kThreads) pcnt[b] = 0;
+    __syncthreads();
+    for (int e = t; e < T; e += kThreads) {
+      uint32_t loc;
+      const uint32_t d = box_key(e, loc) & ((1u << KB) - 1u);
+      atomicAdd(&pcnt[d >> 1], 1u << ((d & 1u) << 4));
     }
     __syncthreads();
-    // a counting pass over the low 8 (8-bit keys) or 12 key bits that does
-    // not keep the order of ties, then stable 4-bit passes over the rest
-    // (none, one for 16-bit keys, five for float keys); the last pass
-    // splits the words into the omnigram and the reverse map
-    uint32_t* bcnt = reinterpret_cast<uint32_t*>(cnt);
-    global_bucket_pass<W>(x0, x1, T, 16, KT == KEY_U8 ? 8 : 12, bcnt, wsum);
-    if constexpr (KT == KEY_U8) {
-      for (int e = t; e < T; e += kThreads) {
-        const W v = x1[e];
-        om[e] = (uint16_t)v;
-        crev[e] = (uint16_t)(v >> 16);
+    packed_exclusive_scan(pcnt, NW, wsum);
+    __syncthreads();
+    for (int e = t; e < T; e += kThreads) {
+      uint32_t loc;
+      const uint32_t key = box_key(e, loc);
+      const uint32_t d = key & ((1u << KB) - 1u);
+      const uint32_t sh = (d & 1u) << 4;
+      const uint32_t slot = (atomicAdd(&pcnt[d >> 1], 1u << sh) >> sh) & 0xffffu;
+      if (KT == KEY_F32) {
+        x0[slot] = ((W)key << 16) | (W)loc;
+      } else {
+        om[slot] = (uint16_t)loc;
+        crev[slot] = (uint16_t)key;
       }
-      __syncthreads();
-    } else {
-      global_radix_sort<W>(x1, x0, T, 28, KT == KEY_U16 ? 1 : 5, om,
-                           KT == KEY_F32 ? nullptr : crev, KT == KEY_F32 ? kbuf : nullptr, cnt,
-                           wsum);
     }
+    __syncthreads();
+    if (KT == KEY_F32) global_radix_sort<W>(x0, x1, T, 32, 4, om, nullptr, kbuf, cnt, wsum);
   }
   if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)

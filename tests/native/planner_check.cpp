@@ -83,20 +83,30 @@ void check_plan(const mf::ImageDesc& d, int dtype, int lds_max, bool br) {
     return;
   }
   if (d.gs) {
-    const int wb = dtype == MF_F32 ? 8 : 4;
     const long long S = d.slot_bytes;
-    const Reg x0{"scratch x0", 0, (long long)wb * TP};
-    const Reg x1{"scratch x1", d.off_x1, (long long)d.off_x1 + (long long)wb * TP};
-    disjoint({x0, x1}, S, d, dtype, "scratch sort");
-    // after the sort (x1 read by the last pass): omnigram and reverse map in x0
-    const Reg om{"scratch omnigram", dtype == MF_F32 ? d.off_p : 0,
-                 (dtype == MF_F32 ? d.off_p : 0) + 2LL * TP};
-    const Reg crev{"scratch reverse map", dtype == MF_F32 ? 0 : d.off_C,
-                   dtype == MF_F32 ? 4LL * TP : (long long)d.off_C + 2LL * TP};
-    disjoint({om, crev, x1}, S, d, dtype, "scratch bands");
-    if (om.hi > x0.hi || crev.hi > x0.hi) fail("omnigram/reverse map beyond x0", d, dtype);
-    const Reg I{"ordinal image", d.off_I, (long long)d.off_I + ib};
+    // LDS during the sort: packed 16-bit key counters (2^16 for 16-bit and
+    // float keys, 2^8 for 8-bit keys), and the digit counters of the float
+    // keys' stable passes, in region B
+    const long long pc = dtype == MF_U8 ? 512 : 131072;
+    const Reg pcnt{"packed key counters", d.off_B, (long long)d.off_B + pc};
+    disjoint({pcnt, tables}, L, d, dtype, "sort");
     disjoint({counters, tables}, L, d, dtype, "sort");
+    if (dtype == MF_F32) {
+      const Reg x0{"scratch x0", 0, 8LL * TP};
+      const Reg x1{"scratch x1", d.off_x1, (long long)d.off_x1 + 8LL * TP};
+      disjoint({x0, x1}, S, d, dtype, "scratch sort");
+      // the last stable pass reads x1 and writes C32 and the omnigram in x0
+      const Reg om{"scratch omnigram", d.off_p, (long long)d.off_p + 2LL * TP};
+      const Reg crev{"scratch reverse map", 0, 4LL * TP};
+      disjoint({om, crev, x1}, S, d, dtype, "scratch bands");
+      if (om.hi > x0.hi || crev.hi > x0.hi) fail("omnigram/reverse map beyond x0", d, dtype);
+    } else {
+      // the counting pass writes the omnigram and C16 directly
+      const Reg om{"scratch omnigram", 0, 2LL * TP};
+      const Reg crev{"scratch reverse map", d.off_C, (long long)d.off_C + 2LL * TP};
+      disjoint({om, crev}, S, d, dtype, "scratch sort and bands");
+    }
+    const Reg I{"ordinal image", d.off_I, (long long)d.off_I + ib};
     disjoint({I, hist, tables}, L, d, dtype, "bands");
     if (d.ipt * mf::kThreads < T) fail("elements per thread", d, dtype);
     return;
