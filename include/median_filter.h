@@ -364,6 +364,19 @@ int mf_autotune(const void* img, int w, int h, size_t stride_bytes, int dtype,
                 const mf_footprint* fp, int boundary, void* out, hipStream_t stream, int reps,
                 int* best_tile_w, int* best_tile_h, float* best_ms);
 
+/* Batch-aware tuning (not in the paper): tile shapes tuned one image at a
+ * time can slow a batch down (fewer, longer tiles balance worse across the
+ * batch's launches).  For each (dtype, footprint) of the batch, costliest
+ * first, times the batch (mf_plan_create + `reps` mf_plan_launch calls on
+ * `stream` after one warm-up) with that footprint's recorded shape and
+ * with the default shape, and keeps in the tuned-shape table whichever
+ * makes the whole batch faster; footprints without a recorded shape are
+ * left alone.  Synchronous.  Outputs (any may be NULL): batch time before
+ * and after (ms), and the number of footprints whose recorded shape was
+ * dropped.  Later plain calls and plans use the table as left. */
+int mf_plan_autotune(const mf_image_desc* descs, int n, hipStream_t stream, int reps,
+                     float* before_ms, float* after_ms, int* dropped);
+
 /* Tuned-shape table persistence: a JSON array, one object per line with
  * "key", "tile_w", "tile_h", "ms".  Load merges into the table (existing
  * keys are replaced); save writes the whole table.  MF_ERR_INVALID_ARG if

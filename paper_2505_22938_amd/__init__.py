@@ -74,6 +74,8 @@ def lib():
         "mf_plan_groups": ([P, IP, IP], I),
         "mf_plan_destroy": ([P], None),
         "median_filter_batched": ([P, I, P], I),
+        "mf_plan_autotune": ([P, I, P, I, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_float), IP], I),
         "mf_mfma_probe": ([P, P, P, P], I),
         "mf_cnn_conv_forward": ([P, I, I, P, P, I, I, P, P, P], I),
         "mf_cnn_flip_weights": ([P, I, P, P], I),
@@ -485,6 +487,19 @@ class BatchPlan:
 
     def __del__(self):
         self.close()
+
+
+def plan_autotune(items, reps: int = 3, stream=None):
+    """Batch-aware tuning of the tuned-shape table for this batch (see the
+    header): returns (batch ms before, batch ms after, shapes dropped)."""
+    arr = _descs(items)
+    b, a = ctypes.c_float(), ctypes.c_float()
+    d = ctypes.c_int()
+    _check("mf_plan_autotune", lib().mf_plan_autotune(ctypes.cast(arr, ctypes.c_void_p), len(items),
+                                                       _stream_ptr(stream), int(reps),
+                                                       ctypes.byref(b), ctypes.byref(a),
+                                                       ctypes.byref(d)))
+    return b.value, a.value, d.value
 
 
 def median_filter_batched(items, stream=None):

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "mf_internal.h"
@@ -402,6 +403,80 @@ int mf_plan_groups(const mf_plan* p, int* groups, int* streams) {
   if (!p) return MF_ERR_INVALID_ARG;
   if (groups) *groups = (int)p->groups.size();
   if (streams) *streams = p->groups.empty() ? 0 : p->nlanes;
+  return MF_OK;
+}
+
+int mf_plan_autotune(const mf_image_desc* descs, int n, hipStream_t stream, int reps,
+                     float* before_ms, float* after_ms, int* dropped) {
+  using namespace mf;
+  if (n < 0 || (n > 0 && !descs) || reps < 1) return MF_ERR_INVALID_ARG;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return MF_ERR_HIP;
+  }
+  // batch time (ms per launch) under the tuned table as it stands
+  auto time_batch = [&](float* ms) -> int {
+    mf_plan* p = nullptr;
+    int rc = mf_plan_create(descs, n, nullptr, &p);
+    if (rc) return rc;
+    rc = mf_plan_launch(p, stream);
+    if (!rc && hipEventRecord(e0, stream) != hipSuccess) rc = MF_ERR_HIP;
+    for (int i = 0; i < reps && !rc; ++i) rc = mf_plan_launch(p, stream);
+    if (!rc && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      rc = MF_ERR_HIP;
+    float t = 0;
+    if (!rc) (void)hipEventElapsedTime(&t, e0, e1);
+    mf_plan_destroy(p);
+    *ms = t / (float)reps;
+    return rc;
+  };
+  // distinct (dtype, footprint) pairs with their share of the batch's work
+  struct Grp {
+    int dtype;
+    const mf_footprint* fp;
+    double cost;
+  };
+  std::vector<Grp> grps;
+  for (int i = 0; i < n; ++i) {
+    const mf_image_desc& e = descs[i];
+    if (!e.fp || !e.w || !e.h) continue;
+    const double c = (double)e.w * e.h * (2.0 * (e.fp->dx_max - e.fp->dx_min + 1) + 160.0);
+    const std::string k = tune_key(e.dtype, e.fp);
+    bool found = false;
+    for (Grp& g : grps)
+      if (g.dtype == e.dtype && tune_key(g.dtype, g.fp) == k) {
+        g.cost += c;
+        found = true;
+        break;
+      }
+    if (!found) grps.push_back({e.dtype, e.fp, c});
+  }
+  std::stable_sort(grps.begin(), grps.end(), [](const Grp& a, const Grp& b) { return a.cost > b.cost; });
+  float best = 0;
+  int rc = time_batch(&best);
+  const float first = best;
+  int ndrop = 0;
+  for (const Grp& g : grps) {
+    if (rc) break;
+    int tw = 0, th = 0;
+    if (!tuned_shape(g.dtype, g.fp, &tw, &th)) continue;
+    erase_tuned_shape(g.dtype, g.fp);
+    float t = 0;
+    if ((rc = time_batch(&t))) break;
+    if (t < best) {
+      best = t;
+      ++ndrop;
+    } else {
+      record_tuned_shape(g.dtype, g.fp, tw, th, 0.0);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (before_ms) *before_ms = first;
+  if (after_ms) *after_ms = best;
+  if (dropped) *dropped = ndrop;
   return MF_OK;
 }
 

@@ -139,6 +139,7 @@ int release_scratch();
 std::string tune_key(int dtype, const mf_footprint* fp);
 bool tuned_shape(int dtype, const mf_footprint* fp, int* tw, int* th);
 void record_tuned_shape(int dtype, const mf_footprint* fp, int tw, int th, double ms);
+void erase_tuned_shape(int dtype, const mf_footprint* fp);
 int tune_cache_load(const char* path);
 int tune_cache_save(const char* path);
 

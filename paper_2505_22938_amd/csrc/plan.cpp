@@ -502,6 +502,12 @@ void record_tuned_shape(int dtype, const mf_footprint* fp, int tw, int th, doubl
   g_tune[k] = {tw, th, ms};
 }
 
+void erase_tuned_shape(int dtype, const mf_footprint* fp) {
+  const std::string k = tune_key(dtype, fp);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.erase(k);
+}
+
 // Cache format: a JSON array with one object per line,
 //   {"key": "<tune_key>", "tile_w": 64, "tile_h": 128, "ms": 2.16}
 int tune_cache_load(const char* path) {

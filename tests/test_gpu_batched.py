@@ -211,3 +211,30 @@ def test_batched_degenerate_images(mf, oracle_mod):
         if e is not None:
             assert np.array_equal(out.cpu().numpy(), e), d.shape
     plan.close()
+
+
+def test_batch_aware_tuning_keeps_results_exact(mf, oracle_mod):
+    """mf_plan_autotune: per-image tuned shapes are recorded first, then the
+    batch tuner keeps each only where the whole batch runs faster.  The
+    batch time never gets worse, and plans built afterwards (whatever
+    shapes the table holds) still match the oracle bit for bit."""
+    items, hosts = small_batch(mf, seed=11, n=10, size_hi=400, r_hi=40)
+    seen = set()
+    for (d, out, fp, b), (img, r, _) in zip(items, hosts):
+        key = (str(img.dtype), r)
+        if key not in seen:
+            seen.add(key)
+            mf.autotune(d, fp, b, out=out, reps=1)
+    before, after, dropped = mf.plan_autotune(items, reps=2)
+    assert before > 0 and after > 0 and after <= before
+    assert 0 <= dropped <= len(seen)
+    plan = mf.BatchPlan(items)
+    plan.launch()
+    torch.cuda.synchronize()
+    check(items, hosts, oracle_mod, "after batch tuning")
+    plan.close()
+    with pytest.raises(mf.MedianFilterError):
+        mf.lib()  # library loaded; bad arguments are rejected on the host
+        import ctypes
+        rc = mf.lib().mf_plan_autotune(None, 3, None, 1, None, None, None)
+        mf._check("mf_plan_autotune", rc)
