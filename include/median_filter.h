@@ -142,6 +142,29 @@ int median_filter_rank(const void* img, int w, int h, size_t stride_bytes, int d
                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Chained tiles (paper, "Method Summary" step 6, forwarding last-row
+ * solutions to the tile below; "Limitations and Future Work", ordinal
+ * transform redundancy: reusing the ranking of the overlap of adjacent
+ * input tiles).
+ *
+ * Same result as median_filter.  One workgroup walks `chain` (>= 1) tiles
+ * of a tile column top to bottom.  Each tile after the first keeps the
+ * part of its input box it shares with the tile above, already in ordinal
+ * order, sorts only its new rows and merges the two by rank, and starts
+ * its first band from the medians of the row above it, whose pixels'
+ * offsets from their window centres carry over (the kept part keeps its
+ * relative order, so each forwarded pixel has exactly the median rank's
+ * count below it).  Windows whose box needs the global-scratch sort
+ * (MF_ERR_UNSUPPORTED) are not chained.  On this GPU it is slower than
+ * median_filter (tiles of a column run one after another and the merge
+ * costs about what the saved sort did); it is provided for completeness
+ * and measurement.
+ * ------------------------------------------------------------------------ */
+int median_filter_chained(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          const mf_footprint* fp, int boundary, int chain, void* out,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Allocation-free median filter, for callers that cannot allocate device
  * memory: code under graph capture, tight serving loops, hosts that forbid
  * hipMalloc.

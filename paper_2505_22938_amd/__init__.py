@@ -55,6 +55,7 @@ def lib():
         "median_filter": ([P, I, I, SZ, I, P, I, P, P], I),
         "median_filter_rank": ([P, I, I, SZ, I, P, I, I, P, P], I),
         "median_filter_noalloc": ([P, I, I, SZ, I, P, I, P, P], I),
+        "median_filter_chained": ([P, I, I, SZ, I, P, I, I, P, P], I),
         "median_filter_ranks": ([P, I, I, SZ, I, P, I, P, I, P], I),
         "median_filter_rank_map": ([P, I, I, SZ, I, P, I, P, SZ, P, P], I),
         "median_filter_windows": ([P, I, I, SZ, I, I, P, I, P], I),
@@ -242,6 +243,24 @@ def median_filter(img, fp: Footprint, boundary: str = "clamp", out=None, rank: i
                                   fp.handle, BOUNDARY[boundary], int(rank),
                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
         _check("median_filter_rank", rc)
+    return out
+
+
+def median_filter_chained(img, fp: Footprint, chain: int, boundary: str = "clamp", out=None,
+                          stream=None):
+    """median_filter with chained tiles: `chain` tiles of a tile column per
+    workgroup, top to bottom, each re-ranking the box part it shares with
+    the tile above and starting from its forwarded last-row solutions."""
+    import torch
+    code, es, w, h, stride_bytes = _plane_args(img)
+    if out is None:
+        out = torch.empty_strided(img.shape, img.stride(), dtype=img.dtype, device=img.device)
+    elif out.shape != img.shape or out.dtype != img.dtype or out.stride() != img.stride():
+        raise ValueError("out must match img in shape, dtype and strides")
+    rc = lib().median_filter_chained(ctypes.c_void_p(img.data_ptr()), w, h, stride_bytes, code,
+                                     fp.handle, BOUNDARY[boundary], int(chain),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _check("median_filter_chained", rc)
     return out
 
 

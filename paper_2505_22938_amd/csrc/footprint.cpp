@@ -265,6 +265,31 @@ size_t footprint_span_table(const mf_footprint* fp, int16_t* dst) {
   return 2 * (nr + nc);
 }
 
+const mf_footprint* footprint_with_top_row(const mf_footprint* fp) {
+  static std::mutex mu;
+  static std::vector<std::pair<std::string, mf_footprint*>> cache;
+  const std::string k = tune_key(MF_U16, fp);
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : cache)
+    if (e.first == k) return e.second;
+  auto* x = new mf_footprint;
+  x->kind = fp->kind;
+  x->limit = fp->limit;
+  x->dx_min = fp->dx_min;
+  x->dx_max = fp->dx_max;
+  x->dy_min = fp->dy_min - 1;
+  x->dy_max = fp->dy_max;
+  x->taps = fp->taps;
+  x->row_lo.push_back(1);   // an empty span: no pixel of this row is in the window
+  x->row_hi.push_back(0);
+  x->row_lo.insert(x->row_lo.end(), fp->row_lo.begin(), fp->row_lo.end());
+  x->row_hi.insert(x->row_hi.end(), fp->row_hi.begin(), fp->row_hi.end());
+  x->col_lo = fp->col_lo;
+  x->col_hi = fp->col_hi;
+  cache.emplace_back(k, x);
+  return x;
+}
+
 int footprint_device_table(const mf_footprint* fp, int device, const void** table,
                            hipStream_t stream) {
   std::lock_guard<std::mutex> lock(fp->mu);

@@ -39,6 +39,23 @@ __global__ __launch_bounds__(kThreads) void mf_plain_gs_kernel(ImageDesc a) {
   }
 }
 
+// Chained tiles: workgroup (x, c) walks tiles c * S .. c * S + S - 1 of
+// tile column x top to bottom, each tile after the first re-ranking the
+// box part it shares with the one above and starting its first band from
+// the forwarded last-row solutions (tile_body, CHAIN).
+template <int KT, int SHAPE, int IMAX>
+__global__ __launch_bounds__(kThreads) void mf_chain_kernel(ImageDesc a, int S) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tx = (int)blockIdx.x % a.tiles_x;
+  const int ty0 = ((int)blockIdx.x / a.tiles_x) * S;
+  const int ty1 = min(ty0 + S, a.tiles_y);
+  for (int ty = ty0; ty < ty1; ++ty) {
+    tile_body<KT, SHAPE, IMAX, false, false, false, true>(a, ty * a.tiles_x + tx, smem, nullptr,
+                                                         ty > ty0 ? 1 : 0);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- host side
 
 namespace {
@@ -67,6 +84,27 @@ KernelFn pick_kernel(const ImageDesc& d) {
                                                    : pick_variant<KEY_U16, SHAPE_SPANS>(d);
   return d.shape == SHAPE_DISC ? pick_variant<KEY_F32, SHAPE_DISC>(d)
                                : pick_variant<KEY_F32, SHAPE_SPANS>(d);
+}
+
+using ChainFn = void (*)(ImageDesc, int);
+
+template <int KT, int SHAPE>
+ChainFn pick_chain_imax(int imax) {
+  switch (imax) {
+    case 9: return mf_chain_kernel<KT, SHAPE, 9>;
+    case 17: return mf_chain_kernel<KT, SHAPE, 17>;
+    case 25: return mf_chain_kernel<KT, SHAPE, 25>;
+    default: return mf_chain_kernel<KT, SHAPE, 33>;
+  }
+}
+
+ChainFn pick_chain(const ImageDesc& d) {
+  if (d.kt == MF_U8) return d.shape == SHAPE_DISC ? pick_chain_imax<KEY_U8, SHAPE_DISC>(d.imax)
+                                                  : pick_chain_imax<KEY_U8, SHAPE_SPANS>(d.imax);
+  if (d.kt == MF_U16) return d.shape == SHAPE_DISC ? pick_chain_imax<KEY_U16, SHAPE_DISC>(d.imax)
+                                                   : pick_chain_imax<KEY_U16, SHAPE_SPANS>(d.imax);
+  return d.shape == SHAPE_DISC ? pick_chain_imax<KEY_F32, SHAPE_DISC>(d.imax)
+                               : pick_chain_imax<KEY_F32, SHAPE_SPANS>(d.imax);
 }
 
 unsigned long long* g_counters = nullptr;  // device work counters, enabled on request
@@ -122,6 +160,38 @@ int launch_plain(const void* img, int w, int h, size_t stride_bytes, int dtype,
   bind_image(&a, img, w, h, stride_bytes, dtype, fp, boundary, rank, table);
   a.out = out;
   return launch_with_plan(a, dev, di, stream);
+}
+
+// Chained tiles (median_filter_chained): the plan of the footprint with an
+// empty row on top, LDS variants only, 128 bytes more LDS for the forwarded
+// locations.
+int launch_chained(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                   const mf_footprint* fp, int boundary, int chain, void* out,
+                   hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MF_ERR_HIP;
+  DeviceInfo di;
+  int rc = device_info(dev, &di);
+  if (rc) return rc;
+  const mf_footprint* fx = footprint_with_top_row(fp);
+  const void* table = nullptr;
+  if ((rc = footprint_device_table(fx, dev, &table, stream))) return rc;
+  ImageDesc a{};
+  if ((rc = choose_plan(dtype, fx, di.lds_max - 128, 33, &a, w, h, di.cus))) return rc;
+  if (a.gs) return MF_ERR_UNSUPPORTED;   // chained tiles re-rank in LDS
+  a.off_fwd = a.lds_bytes;
+  a.lds_bytes += 128;
+  bind_image(&a, img, w, h, stride_bytes, dtype, fx, boundary, (fp->taps - 1) / 2, table);
+  a.out = out;
+  a.counters = g_counters;
+  ChainFn k = pick_chain(a);
+  (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            a.lds_bytes);
+  const long long chains = (long long)a.tiles_x * ((a.tiles_y + chain - 1) / chain);
+  if (chains > 0x7fffffffLL) return MF_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k, dim3((unsigned)chains), dim3(kThreads), a.lds_bytes, stream, a, chain);
+  if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
+  return MF_OK;
 }
 
 int query_plan(int w, int h, int dtype, const mf_footprint* fp, ImageDesc* d) {
@@ -191,6 +261,16 @@ int median_filter(const void* img, int w, int h, size_t stride_bytes, int dtype,
   if (!fp) return MF_ERR_INVALID_ARG;
   return median_filter_rank(img, w, h, stride_bytes, dtype, fp, boundary, (fp->taps - 1) / 2,
                             out, stream);
+}
+
+int median_filter_chained(const void* img, int w, int h, size_t stride_bytes, int dtype,
+                          const mf_footprint* fp, int boundary, int chain, void* out,
+                          hipStream_t stream) {
+  int rc = mf::validate_image(img, w, h, stride_bytes, dtype, fp, boundary, out);
+  if (rc != MF_OK) return rc;
+  if (chain < 1) return MF_ERR_INVALID_ARG;
+  if (w == 0 || h == 0) return MF_OK;
+  return mf::launch_chained(img, w, h, stride_bytes, dtype, fp, boundary, chain, out, stream);
 }
 
 int mf_query_plan(int w, int h, int dtype, const mf_footprint* fp, int* tile_w, int* tile_h,

@@ -94,6 +94,8 @@ struct ImageDesc {
   // (whose box, tables and kernel shape cover all of them)
   int multi_fp;
   PlaneFp pfp[kMaxRankOutputs];
+  // chained tiles: LDS offset of the forwarded last-row locations (64 u16)
+  int off_fwd;
 };
 
 struct DeviceInfo {
@@ -172,6 +174,10 @@ void get_override(int* tw, int* th);
 // MF_ERR_UNSUPPORTED if the table is not there yet and `stream` is capturing.
 int footprint_device_table(const mf_footprint* fp, int device, const void** table,
                            hipStream_t stream);
+// The same footprint with one empty row added above its first row (cached,
+// owned by the library): a box planned for it has one extra row on top, the
+// row whose windows chained tiles forward.
+const mf_footprint* footprint_with_top_row(const mf_footprint* fp);
 // The same table on the host: 2 * (rows + columns) int16 values written to
 // `dst` (which holds at least that many); returns the count.
 size_t footprint_span_table(const mf_footprint* fp, int16_t* dst);

@@ -83,10 +83,13 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* w
 // kout[dst] and the payload to omega[dst].  Without PAYLOAD the element is
 // one word key << 16 | loc; the last pass splits it into loc -> omega[dst]
 // and key -> crev[dst].  KEEP_C = false writes only omega (the caller reads
-// values back from the image through the omnigram's locations).  kbuf/pbuf are the exchange buffers of earlier
+// values back from the image through the omnigram's locations).  WORDS_OUT
+// (without PAYLOAD): the last pass writes the whole words to kbuf as the
+// earlier passes do.  kbuf/pbuf are the exchange buffers of earlier
 // passes; the output arrays may alias them (the last pass reads only
 // registers).
-template <int ITEMS, bool PAYLOAD, bool KEEP_C = true, bool BLOCKED0 = false>
+template <int ITEMS, bool PAYLOAD, bool KEEP_C = true, bool BLOCKED0 = false,
+          bool WORDS_OUT = false>
 __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_t (&pos)[ITEMS],
                                                  int T, int shift0, int passes,
                                                  uint32_t* kbuf, uint16_t* pbuf,
@@ -155,7 +158,7 @@ __device__ __forceinline__ void block_radix_sort(uint32_t (&key)[ITEMS], uint16_
             if (KEEP_C) kout[dst] = key[i];
             omega[dst] = pos[i];
           }
-        } else if (pass + 1 < passes) {
+        } else if (pass + 1 < passes || WORDS_OUT) {
           kbuf[dst] = key[i];
         } else {
           omega[dst] = (uint16_t)key[i];

@@ -633,6 +633,150 @@ __device__ __forceinline__ void br_sort(uint32_t* kbuf, int Ts, int passes, uint
                                  cnt, wsum);
 }
 
+// Branch-free binary search over n sorted values at arr[0 .. n) (LDS):
+// the number of entries whose value (VAL of the entry) is below v (LE:
+// at or below v).
+template <bool LE, typename F>
+__device__ __forceinline__ int count_below(int n, uint32_t v, F val) {
+  int lo = 0;
+  while (n > 0) {
+    const int h = n >> 1;
+    const uint32_t x = val(lo + h);
+    const bool go = LE ? x <= v : x < v;
+    lo = go ? lo + h + 1 : lo;
+    n = go ? n - h - 1 : h;
+  }
+  return lo;
+}
+
+// Chained tiles (paper, "Limitations and Future Work": reuse of the
+// ordinal transform where adjacent input tiles overlap).  The tile below a
+// finished tile in the same column keeps the part of its box the two boxes
+// share, already ranked, and ranks only its new rows:
+//   1. kept entries: the previous omnigram's entries whose box row is at
+//      or below th, in their order, moved up by th rows, values read back
+//      from the image;
+//   2. the new rows (box rows bh - th .. bh - 1) are loaded and sorted;
+//   3. the two sorted lists are merged by rank: a kept entry's ordinal is
+//      its index plus the number of new values below it, a new entry's its
+//      index plus the number of kept values at or below it.  Among equal
+//      values kept entries come first, so the kept pixels keep their
+//      relative order, which keeps forwarded solutions exact.
+// Lists: new entries at 0 .. nn - 1 and kept ones at nn .. T - 1 of kbuf
+// (words key << 16 | location; float keys: keys in kbuf, locations in
+// pbuf).  Output: the omnigram om.
+template <int KT, int IMAX, typename D>
+__device__ __forceinline__ void chain_rerank(const D& a, int gx0, int gy0, uint32_t* kbuf,
+                                             uint16_t* pbuf, uint16_t* om, uint16_t* cnt,
+                                             uint32_t* wsum) {
+  constexpr bool PL = KT == KEY_F32;
+  const int t = threadIdx.x;
+  const int T = a.T, th = a.th, bw = a.bw;
+  const int nn = th * bw;
+  auto pixel = [&](int x, int y) -> uint32_t {
+    const int gx = remap(gx0 + x, a.w, a.boundary), gy = remap(gy0 + y, a.h, a.boundary);
+    const long long off = (long long)gy * a.stride + gx;
+    if (KT == KEY_U8) return static_cast<const uint8_t*>(a.img)[off];
+    if (KT == KEY_U16) return static_cast<const uint16_t*>(a.img)[off];
+    return f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+  };
+  // 1. kept entries, in the previous omnigram's order
+  {
+    uint32_t loc[IMAX];
+    uint32_t nk = 0;
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i) {
+      const int o = t * IMAX + i;
+      const uint32_t l = o < T ? (uint32_t)om[o] : 0u;
+      const bool keep = o < T && (int)(l >> 8) >= th;
+      nk += keep;
+      loc[i] = keep ? (l | 0x10000u) : 0u;
+    }
+    // (the scan's barriers also separate the reads above from the writes)
+    uint32_t pos = (uint32_t)nn + block_exclusive_scan(nk, wsum);
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i) {
+      if (loc[i] & 0x10000u) {
+        const int x = (int)(loc[i] & 255u), y = (int)((loc[i] >> 8) & 255u) - th;
+        const uint32_t nl = (uint32_t)((y << 8) | x);
+        const uint32_t v = pixel(x, y);
+        if (PL) {
+          kbuf[pos] = v;
+          pbuf[pos] = (uint16_t)nl;
+        } else {
+          kbuf[pos] = (v << 16) | nl;
+        }
+        ++pos;
+      }
+    }
+  }
+  // 2. the new rows, loaded in row order and sorted (words to kbuf[0, nn))
+  {
+    uint32_t key[IMAX];
+    uint16_t pos[IMAX];
+    const int r0 = a.bh - th;
+    int lx = t % bw, ly = t / bw;
+    const int sx = kThreads % bw, sy = kThreads / bw;
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i) {
+      const int e = i * kThreads + t;
+      const uint32_t p = (uint32_t)(((r0 + ly) << 8) | lx);
+      const uint32_t v = e < nn ? pixel(lx, r0 + ly) : 0u;
+      key[i] = e < nn ? (PL ? v : ((v << 16) | p)) : 0u;
+      pos[i] = (uint16_t)p;
+      lx += sx;
+      ly += sy;
+      if (lx >= bw) {
+        lx -= bw;
+        ly += 1;
+      }
+    }
+    __syncthreads();   // kept entries written
+    uint32_t* bcnt = reinterpret_cast<uint32_t*>(cnt);
+    if constexpr (KT == KEY_U8) {
+      bucket_pass<IMAX, false, false>(key, pos, nn, 16, 8, kbuf, pbuf, om, bcnt, wsum);
+    } else {
+      const int sh = PL ? 0 : 16;
+      bucket_pass<IMAX, PL, false>(key, pos, nn, sh, 12, kbuf, pbuf, om, bcnt, wsum);
+#pragma unroll
+      for (int i = 0; i < IMAX; ++i) {
+        const int e = t * IMAX + i;
+        key[i] = e < nn ? kbuf[e] : 0u;
+        if (PL) pos[i] = e < nn ? pbuf[e] : (uint16_t)0;
+      }
+      if constexpr (PL)
+        block_radix_sort<IMAX, true, true, true>(key, pos, nn, 12, 5, kbuf, pbuf, pbuf, nullptr,
+                                                 kbuf, cnt, wsum);
+      else
+        block_radix_sort<IMAX, false, false, true, true>(key, pos, nn, 28, 1, kbuf, pbuf, om,
+                                                         nullptr, nullptr, cnt, wsum);
+    }
+  }
+  // 3. merge by rank
+  {
+    const int nk = T - nn;
+    auto val = [&](int e) -> uint32_t { return PL ? kbuf[e] : kbuf[e] >> 16; };
+    uint32_t res[IMAX];
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i) {
+      const int e = t * IMAX + i;
+      res[i] = 0;
+      if (e < T) {
+        const uint32_t v = val(e);
+        const uint32_t l = PL ? (uint32_t)pbuf[e] : (kbuf[e] & 0xffffu);
+        const int r = e < nn ? e + count_below<true>(nk, v, [&](int j) { return val(nn + j); })
+                             : (e - nn) + count_below<false>(nn, v, [&](int j) { return val(j); });
+        res[i] = ((uint32_t)r << 16) | l;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IMAX; ++i)
+      if (t * IMAX + i < T) om[res[i] >> 16] = (uint16_t)(res[i] & 0xffffu);
+    __syncthreads();
+  }
+}
+
 // One output tile.  All threads of the workgroup must call it.
 // GS = false: the sort, the omnigram and the reverse map live in LDS.
 // GS = true: they live in the workgroup's global scratch slot `gslot`
@@ -652,9 +796,24 @@ __device__ __forceinline__ void br_sort(uint32_t* kbuf, int Ts, int passes, uint
 // writing a.outs[q] at a.ranks[q] or at the per-pixel ranks of a.rmaps[q],
 // all from the one ordinal transform of the tile (the paper's
 // multi-parameter and varying-percentile filtering).
-template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false, bool GEN = false, typename D>
+//
+// CHAIN (chained tiles, LDS variant, median only): `chain` = 1 for a tile
+// whose upper neighbour in the column was just processed by this
+// workgroup: its box is re-ranked from the neighbour's (chain_rerank) and
+// its first band starts from the forwarded last-row solutions of the
+// neighbour (paper, "Method Summary" step 6: the median pixel's offset from
+// its window centre carries over, so its ordinal in the new tile is the
+// pivot, with exactly rank-k members below it).  The plan's footprint has
+// one empty row added on top, so the box holds the window of the row above
+// the tile.  Each tile leaves the box locations of its last row's medians
+// in the LDS array at a.off_fwd.
+template <int KT, int SHAPE, int IMAX, bool GS, bool BR = false, bool GEN = false,
+          bool CHAIN = false, typename D>
 __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* smem,
-                                          unsigned char* gslot) {
+                                          unsigned char* gslot, int chain = 0) {
+  static_assert(!(CHAIN && (GS || BR || GEN)), "chained tiles: LDS median tiles only");
+  const bool fw = CHAIN && chain != 0;   // forwarded solutions and a kept box part
+  uint16_t* fwd = CHAIN ? reinterpret_cast<uint16_t*>(smem + a.off_fwd) : nullptr;
   static_assert(!(GS && BR), "bracketed tiles use the LDS variant");
   static_assert(!(GEN && BR), "bracketed tiles compute the median only");
   const int T = a.T;
@@ -865,6 +1024,10 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     Tv = Ts + 1;
     mlo = 1;
   } else if constexpr (!GS) {
+   if (fw) {
+    chain_rerank<KT, IMAX>(a, gx0, gy0, kbuf, pbuf, om, cnt, wsum);
+    clk_load = a.counters ? (long long)clock64() : 0;
+   } else {
     // 1. load the box (striped order)
     uint32_t key[IMAX];
     uint16_t pos[IMAX];
@@ -919,6 +1082,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       block_radix_sort<IMAX, PL, false, true>(key, pos, T, sh + 12, PL ? 5 : 1, kbuf, pbuf, om,
                                               nullptr, nullptr, cnt, wsum);
     }
+   }
   } else {
     // One counting pass over the low 16 bits of the key (8-bit keys: all
     // 8): box pixels are counted per key value straight from the image by
@@ -1062,7 +1226,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       const int ch = r0 + g;
       const int sb = ch / nchb, c0 = (ch - sb * nchb) << 4;
       const int brow = (wid * segs + sb) * R;
-      const bool ok = ch < nch && brow < a.th && ty0 + brow < a.h;
+      const bool ok = ch < nch && brow < a.th && ty0 + brow < a.h && !(fw && wid == 0 && sb == 0);
       const int len = ok ? min(16, cols_in - c0) : 0;
       const int cy = brow - a.dy_min;
       // ranks of the chunk's pixels, lane j holding column c0 + j
@@ -1079,7 +1243,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
         if (chg >= nch) break;
         const int sg = chg / nchb, c0g = (chg - sg * nchb) << 4;
         const int browg = (wid * segs + sg) * R;
-        if (browg >= a.th || ty0 + browg >= a.h) continue;
+        if (browg >= a.th || ty0 + browg >= a.h || (fw && wid == 0 && sg == 0)) continue;
         const int kseed = GEN ? __builtin_amdgcn_readlane(krow, 16 * gg) : k0;
         const int cyg = browg - a.dy_min;
         const long long cs0 = a.counters ? (long long)clock64() : 0;
@@ -1177,11 +1341,21 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   }
   if (a.counters) seed_taps = seeds;  // taps per seed added on the host
   const long long clk2 = a.counters ? (long long)clock64() : 0;
+  // forwarded first row of the tile's first band: the pivot is the new
+  // ordinal of the pixel that was the median of the window one row up
+  const bool fw_lanes = fw && wid == 0 && seg == 0 && lane < tw && col < cols_in;
+  if (fw_lanes) {
+    const uint32_t l = fwd[col];
+    vp = I[((int)(l >> 8) - a.th) * a.pitch + (int)(l & 255u)];
+    vc = k0;
+  }
   {
     const int gx = tx0 + col, gy = ty0 + row0;
-    const bool own = lane < segs * tw && col < cols_in && row0 < a.th && gy < a.h;
+    const bool own = lane < segs * tw && col < cols_in && row0 < a.th && gy < a.h &&
+                     !(fw && wid == 0 && seg == 0);
     if (own && !miss) store_out<KT, GATHER>(a, outq, gx, gy, kbuf, crev, om, m, blo, gx0, gy0);
     if (BR) push_misses(a, own && miss, gx, gy);
+    if (CHAIN && own && row0 == a.th - 1) fwd[col] = om[m];
   }
 
   // 4b. vertical sweep down each band (lanes whose column or row is
@@ -1190,8 +1364,10 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   const int rows_lim = min(a.h - ty0, a.th);   // tile rows inside the image
   const int rows_in = rows_lim - row0;          // rows of this lane's band inside both
   const int r_end = min(R, __builtin_amdgcn_readfirstlane(max(0, rows_lim - wid * segs * R)));
-  for (int r = 1; r < r_end; ++r) {
-    const bool lane_active = in_cols && r < rows_in;
+  // (the forwarded band starts one row higher, at the row above the tile)
+  const int r_begin = fw && wid == 0 ? 0 : 1;
+  for (int r = r_begin; r < r_end; ++r) {
+    const bool lane_active = in_cols && r < rows_in && (r > 0 || fw_lanes);
     const int gx = tx0 + col, gy = ty0 + row0 + r;
     const int kl = rank_at<GEN>(a, q, k0, gx, gy, lane_active);
     const int cy_prev = row0 + r - 1 - a.dy_min;
@@ -1260,6 +1436,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     if (lane_active && !esc)
       store_out<KT, GATHER>(a, outq, gx, gy, kbuf, crev, om, m, blo, gx0, gy0);
     if (BR) push_misses(a, lane_active && esc, gx, gy);
+    if (CHAIN && lane_active && row0 + r == a.th - 1) fwd[col] = om[m];
   }
   if (a.counters) {
     const long long clk3 = (long long)clock64();

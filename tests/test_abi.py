@@ -139,6 +139,10 @@ def test_argument_validation_is_host_side():
     assert nf(P(4096), 8, 8, 8, 0, fp.handle, 0, P(4096 + 16), None) == -2
     assert nf(P(4096), 8, 0, 8, 0, fp.handle, 0, P(1 << 20), None) == 0
     assert L.mf_status_string(-6) == b"MF_ERR_SCRATCH_LIMIT"
+    cf = L.median_filter_chained
+    assert cf(None, 8, 8, 8, 0, fp.handle, 0, 2, P(4096), None) == -1
+    assert cf(P(4096), 8, 8, 8, 0, fp.handle, 0, 0, P(1 << 20), None) == -1      # chain < 1
+    assert cf(P(4096), 8, 8, 8, 0, fp.handle, 0, 2, P(4096 + 16), None) == -2
 
 
 def test_query_plan_geometry():
