@@ -63,6 +63,17 @@ int mf_cnn_pinball(const float* out, int out_ch, const float* tgt, int ncell, fl
 int mf_cnn_features(const void* img, int w, int h, size_t stride_bytes, int dtype, int radius,
                     void* feat, hipStream_t stream);
 
+/* The whole network for inference in one launch: features (as
+ * mf_cnn_features), three 32-channel ReLU layers and the 16-channel output
+ * layer, writing out f32 [ceil(h/8)][ceil(w/8)][16].  w_bf16[l] and bias[l]
+ * (l = 0..3) are layer l's weights and bias in the layouts above (cout 32,
+ * 32, 32, 16).  Equal bit for bit to mf_cnn_features followed by
+ * mf_cnn_conv_forward in modes 0, 0, 0 and 1; nothing is allocated and no
+ * intermediate activation is written to memory. */
+int mf_cnn_net_forward(const void* img, int w, int h, size_t stride_bytes, int dtype, int radius,
+                       const void* const* w_bf16, const float* const* bias, float* out,
+                       hipStream_t stream);
+
 /* Training targets per cell (f32 [cells][2]): min and max of the median
  * image over the cell, divided by 255 or 65535. */
 int mf_cnn_targets(const void* med, int w, int h, size_t stride_bytes, int dtype, float* tgt,
@@ -100,8 +111,9 @@ int mf_learned_get_grads(const mf_learned* net, float* host);
  * (calibrated on held-out images by the caller). */
 int mf_learned_set_margin(mf_learned* net, float margin);
 
-/* Forward pass over the cells of an 8-bit or 16-bit image: out_cells is
- * f32 [ceil(h/8)][ceil(w/8)][16] (device), channel 0 = lo, 1 = hi. */
+/* Forward pass over the cells of an 8-bit or 16-bit image (one launch,
+ * as mf_cnn_net_forward): out_cells is f32 [ceil(h/8)][ceil(w/8)][16]
+ * (device), channel 0 = lo, 1 = hi. */
 int mf_learned_forward(mf_learned* net, const void* img, int w, int h, size_t stride_bytes,
                        int dtype, int radius, float* out_cells, hipStream_t stream);
 

@@ -84,6 +84,7 @@ def lib():
         "mf_cnn_conv_wgrad": ([P, P, I, I, I, I, P, P, P, P], I),
         "mf_cnn_pinball": ([P, I, P, I, ctypes.c_float, ctypes.c_float, P, P, P], I),
         "mf_cnn_features": ([P, I, I, SZ, I, I, P, P], I),
+        "mf_cnn_net_forward": ([P, I, I, SZ, I, I, P, P, P, P], I),
         "mf_cnn_targets": ([P, I, I, SZ, I, P, P], I),
         "mf_cnn_adam": ([P, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          ctypes.c_float, I, P, P], I),
@@ -576,6 +577,18 @@ class cnn:
         code, es, w, h, sb = _plane_args(img)
         _check("mf_cnn_features", lib().mf_cnn_features(_p(img), w, h, sb, code, radius,
                                                         _p(feat), _stream_ptr(stream)))
+
+    @staticmethod
+    def net_forward(img, radius, weights, biases, out, stream=None):
+        """The four-layer network in one launch: weights[l] bf16 and
+        biases[l] f32 device tensors (cout 32, 32, 32, 16), out f32
+        [ceil(h/8)][ceil(w/8)][16]."""
+        code, es, w, h, sb = _plane_args(img)
+        wl = (ctypes.c_void_p * 4)(*[_p(t) for t in weights])
+        bl = (ctypes.c_void_p * 4)(*[_p(t) for t in biases])
+        _check("mf_cnn_net_forward", lib().mf_cnn_net_forward(
+            _p(img), w, h, sb, code, int(radius), ctypes.cast(wl, ctypes.c_void_p),
+            ctypes.cast(bl, ctypes.c_void_p), _p(out), _stream_ptr(stream)))
 
     @staticmethod
     def targets(med, tgt, stream=None):

@@ -277,6 +277,134 @@ __global__ void features_kernel(const T* __restrict__ img, long long stride, int
   for (int c = 2; c < kC; ++c) f[c] = 0;
 }
 
+// ------------------------------------------------------------------ fused inference
+
+// The whole network in one launch (inference only: no activation is kept).
+// A workgroup computes a 16x16-cell block of the output.  Each 3x3 layer
+// needs one more cell of input on every side, so the block's features are
+// taken over 24x24 cells and the three hidden layers over 22x22, 20x20 and
+// 18x18 cells, all in LDS (two buffers used in turn).  Cells outside the
+// cell grid hold zero at every layer, which is the layer-by-layer kernels'
+// zero padding, so the result equals theirs bit for bit: the MFMA sequence
+// per output cell (tap order, reduction chunks), the bias add, ReLU and bf16
+// rounding are the same, and the cell sums of the features are exact in
+// float32 (at most 64 values below 2^16), whatever their order.
+// A layer's row of output cells is covered by 16-cell MFMA row blocks at
+// x = 0 and x = width - 16; where the two overlap, both write the same
+// values.  Each wave keeps a layer's weight fragments in registers.
+constexpr int kNetOB = 16;          // output cells per block side
+constexpr int kNetIn = kNetOB + 8;  // feature cells per block side
+constexpr int kNetThreads = 512;
+
+struct NetWeights {
+  const uint16_t* w[4];   // bf16 [cout][9][32]
+  const float* b[4];      // f32 [cout]
+};
+
+template <int WIN, int NB, bool LAST>
+__device__ __forceinline__ void net_layer(const uint16_t* __restrict__ in,
+                                          uint16_t* __restrict__ ob, float* __restrict__ gout,
+                                          const uint16_t* __restrict__ wg,
+                                          const float* __restrict__ bias, int oy0, int ox0, int H,
+                                          int W) {
+  constexpr int WOUT = WIN - 2, NXB = WOUT > 16 ? 2 : 1, NW = kNetThreads / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  bf16x8 wb[kTaps][NB];
+  float bco[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    bco[nb] = bias[nb * 16 + r];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) wb[t][nb] = load8(wg + ((nb * 16 + r) * kTaps + t) * kC + 8 * g);
+  }
+  for (int task = wv; task < WOUT * NXB; task += NW) {
+    const int yo = task / NXB, xb = (task % NXB) ? WOUT - 16 : 0;
+    floatx4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+      const int dy = t / 3, dx = t % 3;   // input cell = output cell + (dy - 1, dx - 1) + 1
+      const bf16x8 av = load8(in + ((yo + dy) * WIN + xb + r + dx) * kC + 8 * g);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[t][nb], acc[nb], 0, 0, 0);
+    }
+    const int gy = oy0 + yo;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = nb * 16 + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int xo = xb + 4 * g + i, gx = ox0 + xo;
+        const float v = acc[nb][i] + bco[nb];
+        const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        if (LAST) {
+          if (inside) gout[((long long)gy * W + gx) * 16 + co] = v;
+        } else {
+          ob[(yo * WOUT + xo) * kC + co] = inside ? f32_to_bf16_bits(v > 0.f ? v : 0.f) : (uint16_t)0;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNetThreads) void net_forward_kernel(const T* __restrict__ img,
+                                                                  long long stride, int w, int h,
+                                                                  float inv_max, float rplane,
+                                                                  NetWeights nw,
+                                                                  float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint16_t buf_a[kNetIn * kNetIn * kC];
+  __shared__ __attribute__((aligned(16))) uint16_t buf_b[(kNetIn - 2) * (kNetIn - 2) * kC];
+  const int H = (h + kCell - 1) / kCell, W = (w + kCell - 1) / kCell;
+  const int cx0 = blockIdx.x * kNetOB, cy0 = blockIdx.y * kNetOB;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // features over the 24x24 cells around the block: a wave takes a row of
+  // cells, its lanes adjacent pixels of each pixel row (3 x 64 = 192 pixels)
+  for (int cr = wv; cr < kNetIn; cr += kNetThreads / 64) {
+    const int gcy = cy0 - 4 + cr;
+    float s[3] = {0.f, 0.f, 0.f};
+    if (gcy >= 0 && gcy < H) {
+#pragma unroll
+      for (int py = 0; py < kCell; ++py) {
+        const int y = gcy * kCell + py;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const int x = (cx0 - 4) * kCell + lane + 64 * j;
+          if (y < h && x >= 0 && x < w) s[j] += (float)img[(long long)y * stride + x];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      s[j] += __shfl_xor(s[j], 1, 64);
+      s[j] += __shfl_xor(s[j], 2, 64);
+      s[j] += __shfl_xor(s[j], 4, 64);
+    }
+    const int k = lane & 7;   // this lane writes channels 4k .. 4k+3
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int cc = (lane >> 3) + 8 * j, gcx = cx0 - 4 + cc;
+      uint2 v = make_uint2(0u, 0u);
+      if (k == 0 && gcy >= 0 && gcy < H && gcx >= 0 && gcx < W) {
+        const int n = min(kCell, w - gcx * kCell) * min(kCell, h - gcy * kCell);
+        v.x = (uint32_t)f32_to_bf16_bits(s[j] / (float)n * inv_max) |
+              ((uint32_t)f32_to_bf16_bits(rplane) << 16);
+      }
+      *reinterpret_cast<uint2*>(buf_a + (cr * kNetIn + cc) * kC + 4 * k) = v;
+    }
+  }
+  __syncthreads();
+  net_layer<kNetIn, 2, false>(buf_a, buf_b, nullptr, nw.w[0], nw.b[0], cy0 - 3, cx0 - 3, H, W);
+  __syncthreads();
+  net_layer<kNetIn - 2, 2, false>(buf_b, buf_a, nullptr, nw.w[1], nw.b[1], cy0 - 2, cx0 - 2, H, W);
+  __syncthreads();
+  net_layer<kNetIn - 4, 2, false>(buf_a, buf_b, nullptr, nw.w[2], nw.b[2], cy0 - 1, cx0 - 1, H, W);
+  __syncthreads();
+  net_layer<kNetIn - 6, 1, true>(buf_b, nullptr, out, nw.w[3], nw.b[3], cy0, cx0, H, W);
+}
+
 // Training targets per cell: min and max of the exact median image / maxval.
 template <typename T>
 __global__ void targets_kernel(const T* __restrict__ med, long long stride, int w, int h,
@@ -418,6 +546,35 @@ int mf_cnn_features(const void* img, int w, int h, size_t stride_bytes, int dtyp
     hipLaunchKernelGGL(mf::features_kernel<uint16_t>, dim3((ncell + 255) / 256), dim3(256), 0,
                        stream, static_cast<const uint16_t*>(img), (long long)(stride_bytes / 2), w,
                        h, 1.0f / 65535.0f, rp, static_cast<uint16_t*>(feat));
+  return launch_ok();
+}
+
+int mf_cnn_net_forward(const void* img, int w, int h, size_t stride_bytes, int dtype, int radius,
+                       const void* const* w_bf16, const float* const* bias, float* out,
+                       hipStream_t stream) {
+  if (!img || !out || !w_bf16 || !bias || w <= 0 || h <= 0 || radius < 0 ||
+      (dtype != MF_U8 && dtype != MF_U16))
+    return MF_ERR_INVALID_ARG;
+  const size_t es = dtype == MF_U8 ? 1 : 2;
+  if (stride_bytes < (size_t)w * es || stride_bytes % es) return MF_ERR_INVALID_ARG;
+  mf::NetWeights nw;
+  for (int l = 0; l < 4; ++l) {
+    if (!w_bf16[l] || !bias[l]) return MF_ERR_INVALID_ARG;
+    nw.w[l] = static_cast<const uint16_t*>(w_bf16[l]);
+    nw.b[l] = bias[l];
+  }
+  const int H = (h + 7) / 8, W = (w + 7) / 8;
+  const dim3 grid((unsigned)((W + mf::kNetOB - 1) / mf::kNetOB),
+                  (unsigned)((H + mf::kNetOB - 1) / mf::kNetOB));
+  const float rp = radius / 64.0f;
+  if (dtype == MF_U8)
+    hipLaunchKernelGGL(mf::net_forward_kernel<uint8_t>, grid, dim3(mf::kNetThreads), 0, stream,
+                       static_cast<const uint8_t*>(img), (long long)stride_bytes, w, h,
+                       1.0f / 255.0f, rp, nw, out);
+  else
+    hipLaunchKernelGGL(mf::net_forward_kernel<uint16_t>, grid, dim3(mf::kNetThreads), 0, stream,
+                       static_cast<const uint16_t*>(img), (long long)(stride_bytes / 2), w, h,
+                       1.0f / 65535.0f, rp, nw, out);
   return launch_ok();
 }
 

@@ -284,6 +284,9 @@ struct mf_learned {
   float* wsp = nullptr;
   long long wsp_floats = 0;
   float* loss_part = nullptr;
+  // inference output (f32 [cells][16]) of the one-launch forward pass
+  float* iout = nullptr;
+  long long iout_cap = 0;
   // tile workspace
   long long tiles_cap = 0;
   uint2* brackets = nullptr;
@@ -375,7 +378,35 @@ int footprint_radius(const mf_footprint* fp) {
   return std::max(std::max(-fp->dx_min, fp->dx_max), std::max(-fp->dy_min, fp->dy_max));
 }
 
-// Forward pass over the cells of an image; results in n->out.
+// Inference output buffer for an H x W cell grid.
+int ensure_iout(mf_learned* n, long long cells) {
+  if (cells <= n->iout_cap) return MF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) return MF_ERR_HIP;
+  (void)hipFree(n->iout);
+  n->iout = nullptr;
+  n->iout_cap = 0;
+  if (hipMalloc(&n->iout, cells * 16 * 4) != hipSuccess) return MF_ERR_NOMEM;
+  n->iout_cap = cells;
+  return MF_OK;
+}
+
+// Inference: the whole network in one launch; results in n->iout.
+int net_infer(mf_learned* n, const void* img, int w, int h, size_t stride, int dtype, int radius,
+              hipStream_t s) {
+  const long long cells = (long long)((w + 7) / 8) * ((h + 7) / 8);
+  int rc = ensure_iout(n, cells);
+  if (rc) return rc;
+  const void* wl[4];
+  const float* bl[4];
+  for (int l = 0; l < 4; ++l) {
+    wl[l] = n->wbf + mf::kOffW[l];
+    bl[l] = n->p + mf::kOffB[l];
+  }
+  return mf_cnn_net_forward(img, w, h, stride, dtype, radius, wl, bl, n->iout, s);
+}
+
+// Training forward pass over the cells of an image (every activation
+// kept for the backward pass); results in n->out.
 int net_forward(mf_learned* n, const void* img, int w, int h, size_t stride, int dtype,
                 int radius, hipStream_t s) {
   const int H = (h + 7) / 8, W = (w + 7) / 8;
@@ -521,6 +552,7 @@ void mf_learned_destroy(mf_learned* n) {
   (void)hipFree(n->fail_px);
   (void)hipFree(n->miss_count);
   (void)hipFree(n->miss);
+  (void)hipFree(n->iout);
   delete n;
 }
 
@@ -609,10 +641,10 @@ int mf_learned_forward(mf_learned* n, const void* img, int w, int h, size_t stri
   if (!n || !img || !out_cells || w <= 0 || h <= 0 || radius < 0 ||
       (dtype != MF_U8 && dtype != MF_U16))
     return MF_ERR_INVALID_ARG;
-  int rc = net_forward(n, img, w, h, stride_bytes, dtype, radius, s);
+  int rc = net_infer(n, img, w, h, stride_bytes, dtype, radius, s);
   if (rc) return rc;
   const long long cells = (long long)((w + 7) / 8) * ((h + 7) / 8);
-  return hipMemcpyAsync(out_cells, n->out, cells * 16 * 4, hipMemcpyDeviceToDevice, s) ==
+  return hipMemcpyAsync(out_cells, n->iout, cells * 16 * 4, hipMemcpyDeviceToDevice, s) ==
                  hipSuccess
              ? MF_OK
              : MF_ERR_HIP;
@@ -706,11 +738,11 @@ int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, in
   const long long ntiles = (long long)tiles_x * tiles_y;
   if (ntiles > 0x7fffffffLL / 64 || (long long)w * h > 0xffffffffLL) return MF_ERR_UNSUPPORTED;
   if ((rc = ensure_tiles(net, ntiles)) || (rc = ensure_miss(net, (long long)w * h))) return rc;
-  if ((rc = net_forward(net, img, w, h, stride_bytes, dtype, footprint_radius(fp), stream)))
+  if ((rc = net_infer(net, img, w, h, stride_bytes, dtype, footprint_radius(fp), stream)))
     return rc;
   const float maxval = dtype == MF_U8 ? 255.0f : 65535.0f;
   hipLaunchKernelGGL(mf::bracket_kernel, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, stream,
-                     net->out, net->grid_h, net->grid_w, lp.br.tw, lp.br.th, tiles_x, (int)ntiles,
+                     net->iout, (h + 7) / 8, (w + 7) / 8, lp.br.tw, lp.br.th, tiles_x, (int)ntiles,
                      maxval, net->margin, net->brackets, net->fail_px, net->miss_count);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   return bracketed_filter(net, net->brackets, img, w, h, stride_bytes, dtype, fp, boundary, out,

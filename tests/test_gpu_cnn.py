@@ -207,3 +207,31 @@ def test_adam_step(mf):
     err = np.abs(got - pp)
     assert np.all(err <= tol), float(np.max(err / tol))
     assert np.array_equal(from_bf16(pb), OC.bf16_round(got))
+
+
+@pytest.mark.parametrize("dtype,w,h,radius", [("u16", 37, 53, 16), ("u8", 300, 129, 4),
+                                               ("u16", 1, 1, 32), ("u16", 200, 200, 64),
+                                               ("u8", 512, 384, 0), ("u16", 1000, 17, 8)])
+def test_fused_network_equals_layers(mf, dtype, w, h, radius):
+    """The one-launch network (features + four layers in LDS) against the
+    layer-by-layer kernels on the same bf16 weights: equal bit for bit, on
+    grids that are not multiples of the 16-cell block and on the 1-cell
+    grid (every layer's zero padding matters there)."""
+    import workloads
+    rng = np.random.default_rng(w * 7 + h)
+    img = torch.from_numpy(workloads.uniform(w, h, dtype, w + h)).cuda()
+    layers = [make_layer(rng, 32, cin_real=2), make_layer(rng, 32), make_layer(rng, 32),
+              make_layer(rng, 16)]
+    wd = [to_bf16_dev(wl)[0] for wl, _ in layers]
+    bd = [torch.from_numpy(b.astype(np.float32)).cuda() for _, b in layers]
+    H, W = (h + 7) // 8, (w + 7) // 8
+    act = [torch.empty((H, W, 32), dtype=torch.bfloat16, device="cuda") for _ in range(4)]
+    mf.cnn.features(img, radius, act[0])
+    for l in range(3):
+        mf.cnn.conv_forward(act[l], H, W, wd[l], bd[l], 32, 0, act[l + 1])
+    ref = torch.empty((H, W, 16), dtype=torch.float32, device="cuda")
+    mf.cnn.conv_forward(act[3], H, W, wd[3], bd[3], 16, 1, ref)
+    got = torch.full((H, W, 16), float("nan"), dtype=torch.float32, device="cuda")
+    mf.cnn.net_forward(img, radius, wd, bd, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
