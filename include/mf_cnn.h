@@ -66,8 +66,8 @@ int mf_cnn_features(const void* img, int w, int h, size_t stride_bytes, int dtyp
 /* The whole network for inference in one launch: features (as
  * mf_cnn_features), three 32-channel ReLU layers and the 16-channel output
  * layer, writing out f32 [ceil(h/8)][ceil(w/8)][16].  w_bf16[l] and bias[l]
- * (l = 0..3) are layer l's weights and bias in the layouts above (cout 32,
- * 32, 32, 16).  Equal bit for bit to mf_cnn_features followed by
+ * (l = 0..3) are layer l's weights (16-byte aligned) and bias in the
+ * layouts above (cout 32, 32, 32, 16).  Equal bit for bit to mf_cnn_features followed by
  * mf_cnn_conv_forward in modes 0, 0, 0 and 1; nothing is allocated and no
  * intermediate activation is written to memory. */
 int mf_cnn_net_forward(const void* img, int w, int h, size_t stride_bytes, int dtype, int radius,

@@ -291,10 +291,14 @@ __global__ void features_kernel(const T* __restrict__ img, long long stride, int
 // float32 (at most 64 values below 2^16), whatever their order.
 // A layer's row of output cells is covered by 16-cell MFMA row blocks at
 // x = 0 and x = width - 16; where the two overlap, both write the same
-// values.  Each wave keeps a layer's weight fragments in registers.
+// values.  All four layers' weights are staged in LDS once, tap-major
+// ([tap][cout][32], so the 16 lanes of an MFMA operand read 1 KB of
+// consecutive bytes), while the block's pixels are being read.
 constexpr int kNetOB = 16;          // output cells per block side
 constexpr int kNetIn = kNetOB + 8;  // feature cells per block side
-constexpr int kNetThreads = 512;
+constexpr int kNetThreads = 1024;
+constexpr int kNetW = kTaps * 32 * kC;            // bf16 weights of a 32-channel layer
+constexpr int kNetWAll = 3 * kNetW + kTaps * 16 * kC;
 
 struct NetWeights {
   const uint16_t* w[4];   // bf16 [cout][9][32]
@@ -304,19 +308,15 @@ struct NetWeights {
 template <int WIN, int NB, bool LAST>
 __device__ __forceinline__ void net_layer(const uint16_t* __restrict__ in,
                                           uint16_t* __restrict__ ob, float* __restrict__ gout,
-                                          const uint16_t* __restrict__ wg,
+                                          const uint16_t* __restrict__ ws,
                                           const float* __restrict__ bias, int oy0, int ox0, int H,
                                           int W) {
   constexpr int WOUT = WIN - 2, NXB = WOUT > 16 ? 2 : 1, NW = kNetThreads / 64;
+  constexpr int COUT = 16 * NB;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  bf16x8 wb[kTaps][NB];
   float bco[NB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    bco[nb] = bias[nb * 16 + r];
-#pragma unroll
-    for (int t = 0; t < kTaps; ++t) wb[t][nb] = load8(wg + ((nb * 16 + r) * kTaps + t) * kC + 8 * g);
-  }
+  for (int nb = 0; nb < NB; ++nb) bco[nb] = bias[nb * 16 + r];
   for (int task = wv; task < WOUT * NXB; task += NW) {
     const int yo = task / NXB, xb = (task % NXB) ? WOUT - 16 : 0;
     floatx4 acc[NB];
@@ -327,8 +327,10 @@ __device__ __forceinline__ void net_layer(const uint16_t* __restrict__ in,
       const int dy = t / 3, dx = t % 3;   // input cell = output cell + (dy - 1, dx - 1) + 1
       const bf16x8 av = load8(in + ((yo + dy) * WIN + xb + r + dx) * kC + 8 * g);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[t][nb], acc[nb], 0, 0, 0);
+      for (int nb = 0; nb < NB; ++nb) {
+        const bf16x8 bv = load8(ws + (t * COUT + nb * 16 + r) * kC + 8 * g);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nb], 0, 0, 0);
+      }
     }
     const int gy = oy0 + yo;
 #pragma unroll
@@ -355,14 +357,25 @@ __global__ __launch_bounds__(kNetThreads) void net_forward_kernel(const T* __res
                                                                   float inv_max, float rplane,
                                                                   NetWeights nw,
                                                                   float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint16_t wsm[kNetWAll];
   __shared__ __attribute__((aligned(16))) uint16_t buf_a[kNetIn * kNetIn * kC];
   __shared__ __attribute__((aligned(16))) uint16_t buf_b[(kNetIn - 2) * (kNetIn - 2) * kC];
   const int H = (h + kCell - 1) / kCell, W = (w + kCell - 1) / kCell;
   const int cx0 = blockIdx.x * kNetOB, cy0 = blockIdx.y * kNetOB;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // features over the 24x24 cells around the block: a wave takes a row of
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // weights, 16 bytes per load: source [cout][tap][32] -> LDS [tap][cout][32]
+  for (int i = t; i < kNetWAll / 8; i += kNetThreads) {
+    const int e = i * 8;
+    const int l = e < 3 * kNetW ? e / kNetW : 3;
+    const int cout = l == 3 ? 16 : 32, le = e - l * kNetW;
+    const int co = le / (kTaps * kC), tap = (le / kC) % kTaps, c = le % kC;
+    *reinterpret_cast<uint4*>(wsm + l * kNetW + (tap * cout + co) * kC + c) =
+        *reinterpret_cast<const uint4*>(nw.w[l] + le);
+  }
+  // features over the 24x24 cells around the block: a wave takes rows of
   // cells, its lanes adjacent pixels of each pixel row (3 x 64 = 192 pixels)
-  for (int cr = wv; cr < kNetIn; cr += kNetThreads / 64) {
+  constexpr int NW = kNetThreads / 64;
+  for (int cr = wv; cr < kNetIn; cr += NW) {
     const int gcy = cy0 - 4 + cr;
     float s[3] = {0.f, 0.f, 0.f};
     if (gcy >= 0 && gcy < H) {
@@ -396,13 +409,15 @@ __global__ __launch_bounds__(kNetThreads) void net_forward_kernel(const T* __res
     }
   }
   __syncthreads();
-  net_layer<kNetIn, 2, false>(buf_a, buf_b, nullptr, nw.w[0], nw.b[0], cy0 - 3, cx0 - 3, H, W);
+  net_layer<kNetIn, 2, false>(buf_a, buf_b, nullptr, wsm, nw.b[0], cy0 - 3, cx0 - 3, H, W);
   __syncthreads();
-  net_layer<kNetIn - 2, 2, false>(buf_b, buf_a, nullptr, nw.w[1], nw.b[1], cy0 - 2, cx0 - 2, H, W);
+  net_layer<kNetIn - 2, 2, false>(buf_b, buf_a, nullptr, wsm + kNetW, nw.b[1], cy0 - 2, cx0 - 2,
+                                  H, W);
   __syncthreads();
-  net_layer<kNetIn - 4, 2, false>(buf_a, buf_b, nullptr, nw.w[2], nw.b[2], cy0 - 1, cx0 - 1, H, W);
+  net_layer<kNetIn - 4, 2, false>(buf_a, buf_b, nullptr, wsm + 2 * kNetW, nw.b[2], cy0 - 1,
+                                  cx0 - 1, H, W);
   __syncthreads();
-  net_layer<kNetIn - 6, 1, true>(buf_b, nullptr, out, nw.w[3], nw.b[3], cy0, cx0, H, W);
+  net_layer<kNetIn - 6, 1, true>(buf_b, nullptr, out, wsm + 3 * kNetW, nw.b[3], cy0, cx0, H, W);
 }
 
 // Training targets per cell: min and max of the exact median image / maxval.
@@ -559,7 +574,8 @@ int mf_cnn_net_forward(const void* img, int w, int h, size_t stride_bytes, int d
   if (stride_bytes < (size_t)w * es || stride_bytes % es) return MF_ERR_INVALID_ARG;
   mf::NetWeights nw;
   for (int l = 0; l < 4; ++l) {
-    if (!w_bf16[l] || !bias[l]) return MF_ERR_INVALID_ARG;
+    if (!w_bf16[l] || !bias[l] || (reinterpret_cast<uintptr_t>(w_bf16[l]) & 15u))
+      return MF_ERR_INVALID_ARG;
     nw.w[l] = static_cast<const uint16_t*>(w_bf16[l]);
     nw.b[l] = bias[l];
   }

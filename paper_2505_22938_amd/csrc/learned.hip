@@ -49,13 +49,21 @@ __global__ __launch_bounds__(kThreads) void mf_bracket_tile_kernel(ImageDesc a, 
   if (threadIdx.x == 0) tile_fail[tile] = bad ? 1 : 0;
 }
 
+// The bracketed tile holding fallback tile `tile`: fallback tiles have the
+// bracketed tiles' width and 1/ratio of their height.
+__device__ __forceinline__ int parent_tile(const ImageDesc& f, int tile, int ratio) {
+  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
+  return (ty / ratio) * f.tiles_x + tx;
+}
+
 // Plain pass over the flagged tiles, LDS variant: one workgroup per tile.
 template <int KT, int SHAPE, int IMAX>
 __global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc f, const int* tile_fail,
-                                                               unsigned long long* fail_px) {
+                                                               unsigned long long* fail_px,
+                                                               int ratio) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile_fail[tile] == 0) return;   // uniform per workgroup
+  if (tile_fail[parent_tile(f, tile, ratio)] == 0) return;   // uniform per workgroup
   tile_body<KT, SHAPE, IMAX, false, false>(f, tile, smem, nullptr);
   if (threadIdx.x == 0) count_fallback(f, tile, fail_px);
 }
@@ -65,77 +73,89 @@ __global__ __launch_bounds__(kThreads) void mf_fallback_kernel(ImageDesc f, cons
 template <int KT, int SHAPE>
 __global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
                                                                   const int* tile_fail,
-                                                                  unsigned long long* fail_px) {
+                                                                  unsigned long long* fail_px,
+                                                                  int ratio) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* slot = f.scratch + (long long)blockIdx.x * f.slot_bytes;
   const int ntiles = f.tiles_x * f.tiles_y;
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const int tile = xcd_tile(v, ntiles);
-    if (tile_fail[tile] == 0) continue;   // uniform per workgroup
+    if (tile_fail[parent_tile(f, tile, ratio)] == 0) continue;   // uniform per workgroup
     tile_body<KT, SHAPE, 1, true>(f, tile, smem, slot);
     if (threadIdx.x == 0) count_fallback(f, tile, fail_px);
     __syncthreads();
   }
 }
 
-// Per-pixel exact fallback: one wave per listed pixel (index y * w + x)
-// selects the rank-k value of its window straight from the image by radix
-// selection on the value bits: a 256-bin histogram of the top byte finds
-// the byte holding rank k, then (16-bit) a histogram of the low byte among
-// the values with that top byte.  The window's values are read once, eight
-// footprint rows at a time (their loads in flight together), and kept in
-// LDS for the second histogram when they fit (kStage values per wave;
-// larger windows are read again).  Adds the list length to fail_px.
+// Per-pixel exact fallback: one workgroup (four waves) per listed pixel
+// (index y * w + x) selects the rank-k value of its window straight from
+// the image by radix selection on the value bits: a 256-bin histogram of
+// the top byte finds the byte holding rank k, then (16-bit) a histogram of
+// the low byte among the values with that top byte.  The four waves take
+// the window's rows in turn, sixteen rows of loads in flight per wave, and
+// keep the values in LDS for the second histogram when the window has at
+// most kStage taps (larger windows are read again).  Adds the list length
+// to fail_px.
+constexpr int kSelStage = 8192, kSelMaxRows = 512;
 template <int KT>
 __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
                                                               const unsigned int* miss,
                                                               const unsigned int* miss_count,
                                                               unsigned long long* fail_px) {
-  constexpr int kStage = 4096, kRows = 8;
-  __shared__ uint32_t hist_s[4][256];
-  __shared__ uint16_t stage_s[4][kStage];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t* hist = hist_s[wid];
-  uint16_t* stage = stage_s[wid];
+  constexpr int kRows = 16;
+  __shared__ uint32_t hist[256];
+  __shared__ uint16_t stage[kSelStage];
+  __shared__ int rowbase[kSelMaxRows + 1];   // staged position of each row's first tap
+  __shared__ int sel[2];                     // bin holding rank k, count below the bin
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int n = (int)*miss_count;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(fail_px, (unsigned long long)n);
-  const int nwaves = (int)gridDim.x * 4;
+  if (blockIdx.x == 0 && t == 0 && n > 0) atomicAdd(fail_px, (unsigned long long)n);
+  if ((int)blockIdx.x >= n) return;   // uniform per workgroup
+  const int nrows = f.nrows;          // <= kSelMaxRows (host-checked)
+  // rowbase = exclusive prefix sum of the row widths (wave 0, 64 rows per step)
+  if (wid == 0) {
+    int carry = 0;
+    for (int r0 = 0; r0 <= nrows; r0 += 64) {
+      const int r = r0 + lane;
+      const int wdt = r < nrows ? f.spans[r].y - f.spans[r].x + 1 : 0;
+      const int incl = (int)wave_inclusive_scan((uint32_t)wdt, lane);
+      if (r <= nrows) rowbase[r] = carry + incl - wdt;
+      carry += __shfl(incl, 63, 64);
+    }
+  }
+  __syncthreads();
+  const int N = rowbase[nrows];
+  const bool staged = N <= kSelStage;
   constexpr int kPasses = KT == KEY_U8 ? 1 : 2;
-  for (int i = (int)blockIdx.x * 4 + wid; i < n; i += nwaves) {
+  for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
     const uint32_t idx = miss[i];
     const int y = (int)(idx / (uint32_t)f.w), x = (int)(idx - (uint32_t)y * (uint32_t)f.w);
     int target = f.rank;
     uint32_t prefix = 0;
-    bool staged = true;   // every value of the window is in `stage`
     for (int pass = 0; pass < kPasses; ++pass) {
       const int sh = (kPasses - 1 - pass) * 8;
-      for (int b = lane; b < 256; b += 64) hist[b] = 0;
-      wave_lds_sync();
+      hist[t] = 0;
+      __syncthreads();
       if (pass == 1 && staged) {
-        int pos = 0;
-        for (int r = 0; r < f.nrows; ++r) pos += f.spans[r].y - f.spans[r].x + 1;
-        for (int j = lane; j < pos; j += 64) {
+        for (int j = t; j < N; j += 256) {
           const uint32_t v = stage[j];
           if ((v >> 8) == prefix) atomicAdd(&hist[v & 255u], 1u);
         }
       } else {
-        int base = 0;   // position of the current row's first value in `stage`
-        for (int r0 = 0; r0 < f.nrows; r0 += kRows) {
+        // this wave's rows: wid, wid + 4, ...; kRows of them per batch
+        for (int b0 = wid; b0 < nrows; b0 += 4 * kRows) {
           uint32_t v[kRows][2];
           bool ok[kRows][2];
-          int rb[kRows];
 #pragma unroll
           for (int j = 0; j < kRows; ++j) {
-            const int r = min(r0 + j, f.nrows - 1);
+            const int rr = b0 + 4 * j, r = min(rr, nrows - 1);
             const short2 sp = f.spans[r];
-            rb[j] = base;
-            if (r0 + j < f.nrows) base += sp.y - sp.x + 1;
             const long long rowoff =
                 (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const int dx = sp.x + lane + 64 * q;
-              ok[j][q] = r0 + j < f.nrows && dx <= sp.y;
+              ok[j][q] = rr < nrows && dx <= sp.y;
               const int gx = remap(x + min(dx, (int)sp.y), f.w, f.boundary);
               v[j][q] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
                                      : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
@@ -146,54 +166,52 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
 #pragma unroll
             for (int q = 0; q < 2; ++q)
               if (ok[j][q]) {
-                const int pos = rb[j] + lane + 64 * q;
-                if (pass == 0 && pos < kStage) stage[pos] = (uint16_t)v[j][q];
+                const int pos = rowbase[b0 + 4 * j] + lane + 64 * q;
+                if (pass == 0 && staged) stage[pos] = (uint16_t)v[j][q];
                 if (pass == 0 || (v[j][q] >> 8) == prefix)
                   atomicAdd(&hist[(v[j][q] >> sh) & 255u], 1u);
               }
           // rows wider than 128 taps: the rest one load at a time
-          for (int j = 0; j < kRows && r0 + j < f.nrows; ++j) {
-            const short2 sp = f.spans[r0 + j];
+          for (int j = 0; j < kRows && b0 + 4 * j < nrows; ++j) {
+            const int r = b0 + 4 * j;
+            const short2 sp = f.spans[r];
             const long long rowoff =
-                (long long)remap(y + f.dy_min + r0 + j, f.h, f.boundary) * f.stride;
+                (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
             for (int dx = sp.x + lane + 128; dx <= sp.y; dx += 64) {
               const int gx = remap(x + dx, f.w, f.boundary);
               const uint32_t vv =
                   KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
                                : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
-              const int pos = rb[j] + dx - sp.x;
-              if (pass == 0 && pos < kStage) stage[pos] = (uint16_t)vv;
+              if (pass == 0 && staged) stage[rowbase[r] + dx - sp.x] = (uint16_t)vv;
               if (pass == 1 && (vv >> 8) != prefix) continue;
               atomicAdd(&hist[(vv >> sh) & 255u], 1u);
             }
           }
         }
-        if (pass == 0) staged = base <= kStage;
       }
-      wave_lds_sync();
-      uint32_t h[4];
+      __syncthreads();
+      if (wid == 0) {
+        uint32_t h[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) h[j] = hist[lane * 4 + j];
-      const uint32_t sum = h[0] + h[1] + h[2] + h[3];
-      uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
-      int bin = -1;
-      uint32_t bbase = 0;
+        for (int j = 0; j < 4; ++j) h[j] = hist[lane * 4 + j];
+        const uint32_t sum = h[0] + h[1] + h[2] + h[3];
+        uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (bin < 0 && cum <= (uint32_t)target && (uint32_t)target < cum + h[j]) {
-          bin = lane * 4 + j;
-          bbase = cum;
+        for (int j = 0; j < 4; ++j) {
+          // exactly one bin holds rank `target` (a non-empty one)
+          if (cum <= (uint32_t)target && (uint32_t)target < cum + h[j]) {
+            sel[0] = lane * 4 + j;
+            sel[1] = (int)cum;
+          }
+          cum += h[j];
         }
-        cum += h[j];
       }
-      const uint64_t who = __ballot(bin >= 0);
-      const int src = __ffsll((unsigned long long)who) - 1;   // rank k always exists
-      const int sbin = __builtin_amdgcn_readlane(bin, src);
-      target -= __builtin_amdgcn_readlane((int)bbase, src);
-      prefix = pass == 0 ? (uint32_t)sbin : ((prefix << 8) | (uint32_t)sbin);
-      wave_lds_sync();
+      __syncthreads();
+      target -= sel[1];
+      prefix = pass == 0 ? (uint32_t)sel[0] : ((prefix << 8) | (uint32_t)sel[0]);
+      __syncthreads();   // sel and hist are rewritten by the next pass or pixel
     }
-    if (lane == 0) {
+    if (t == 0) {
       const long long o = (long long)y * f.stride + x;
       if (KT == KEY_U8) static_cast<uint8_t*>(f.out)[o] = (uint8_t)prefix;
       else static_cast<uint16_t*>(f.out)[o] = (uint16_t)prefix;
@@ -422,7 +440,7 @@ int net_forward(mf_learned* n, const void* img, int w, int h, size_t stride, int
 }
 
 using BrKernel = void (*)(mf::ImageDesc, int*);
-using FbKernel = void (*)(mf::ImageDesc, const int*, unsigned long long*);
+using FbKernel = void (*)(mf::ImageDesc, const int*, unsigned long long*, int);
 
 template <int KT, int SHAPE>
 void pick(const mf::ImageDesc& br, const mf::ImageDesc& fb, BrKernel* b, FbKernel* f) {
@@ -444,24 +462,42 @@ void pick(const mf::ImageDesc& br, const mf::ImageDesc& fb, BrKernel* b, FbKerne
   }
 }
 
-// Tile plans of the learned path, both on the tile shape the plain filter
-// would use: the bracketed layout `br`, and the plain layout `fb` (LDS if it
-// fits, else global scratch) of the pass over tiles with too many
-// in-bracket pixels.
+// Tile plans of the learned path: the bracketed layout `br` on the tallest
+// tile shape that fits LDS, and the plain layout `fb` of the pass over the
+// tiles that fail.  The plain pass takes the plain filter's own plan for the
+// image when its tiles split the bracketed tiles evenly (same width, a
+// height dividing theirs: `ratio` fallback tiles per bracketed tile), so a
+// pass over many failed tiles is as well balanced as the plain filter;
+// otherwise the bracketed tiles' shape (LDS if it fits, else global
+// scratch).  Measured on 2048x2048 uint16 (i.i.d. and natural-like, radius
+// 16 and 32): bracketed tiles of the plain filter's shorter shape were
+// slower than the tall ones (radius 32, i.i.d.: 417 against 383 us), and
+// they fail on more pixels.
 struct LearnedPlan {
   mf::ImageDesc br, fb;
   mf::DeviceInfo di;
   int dev;
+  int ratio;
 };
 
-int learned_plan(int dtype, const mf_footprint* fp, LearnedPlan* lp) {
+int learned_plan(int dtype, const mf_footprint* fp, int w, int h, LearnedPlan* lp) {
   if (hipGetDevice(&lp->dev) != hipSuccess) return MF_ERR_HIP;
   int rc = mf::device_info(lp->dev, &lp->di);
   if (rc) return rc;
+  lp->ratio = 1;
+  mf::ImageDesc own{};
+  const bool have_own =
+      w > 0 && h > 0 &&
+      mf::choose_plan(dtype, fp, lp->di.lds_max, 33, &own, w, h, lp->di.cus) == MF_OK;
   mf::ImageDesc base{};
   if ((rc = mf::choose_plan_tall(dtype, fp, lp->di.lds_max, 33, &base))) return rc;
   if ((rc = mf::make_plan_br(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->br)))
     return rc;
+  if (have_own && own.tw == base.tw && own.th <= base.th && base.th % own.th == 0) {
+    lp->fb = own;
+    lp->ratio = base.th / own.th;
+    return MF_OK;
+  }
   if (mf::make_plan(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->fb) != MF_OK ||
       lp->fb.imax > 33)
     if ((rc = mf::make_plan_gs(dtype, fp, lp->di.lds_max, base.tw, base.th, &lp->fb)))
@@ -496,10 +532,11 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
     if (a.shape == mf::SHAPE_DISC) pick<mf::KEY_U16, mf::SHAPE_DISC>(a, f, &bk, &fk);
     else pick<mf::KEY_U16, mf::SHAPE_SPANS>(a, f, &bk, &fk);
   }
-  long long fgrid = ntiles;
+  const long long fntiles = (long long)f.tiles_x * f.tiles_y;
+  long long fgrid = fntiles;
   if (f.gs) {
     const int occ = std::max(1, std::min(2, lp.di.lds_max / std::max(1, f.lds_bytes)));
-    fgrid = std::min<long long>(ntiles, (long long)lp.di.cus * occ);
+    fgrid = std::min<long long>(fntiles, (long long)lp.di.cus * occ);
     void* scr = nullptr;
     if ((rc = mf::get_scratch(lp.dev, s, (size_t)fgrid * (size_t)f.slot_bytes, &scr))) return rc;
     f.scratch = static_cast<unsigned char*>(scr);
@@ -511,8 +548,9 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
   hipLaunchKernelGGL(bk, dim3((unsigned)ntiles), dim3(mf::kThreads), a.lds_bytes, s, a,
                      n->tile_fail);
   hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
-                     (const int*)n->tile_fail, n->fail_px);
-  const long long pgrid = std::max(1, lp.di.cus) * 8LL;   // 32 waves per CU
+                     (const int*)n->tile_fail, n->fail_px, lp.ratio);
+  if (f.nrows > mf::kSelMaxRows) return MF_ERR_UNSUPPORTED;
+  const long long pgrid = std::max(1, lp.di.cus) * 8LL;   // 8 pixels at a time per CU
   if (dtype == MF_U8)
     hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,
                        s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,
@@ -709,7 +747,7 @@ int median_filter_bracketed(const void* img, int w, int h, size_t stride_bytes, 
     return MF_OK;
   }
   LearnedPlan lp;
-  if ((rc = learned_plan(dtype, fp, &lp))) return rc;
+  if ((rc = learned_plan(dtype, fp, w, h, &lp))) return rc;
   const long long ntiles =
       (long long)((w + lp.br.tw - 1) / lp.br.tw) * ((h + lp.br.th - 1) / lp.br.th);
   if (ntiles > 0x7fffffffLL) return MF_ERR_UNSUPPORTED;
@@ -733,7 +771,7 @@ int median_filter_learned(const void* img, int w, int h, size_t stride_bytes, in
     return MF_OK;
   }
   LearnedPlan lp;
-  if ((rc = learned_plan(dtype, fp, &lp))) return rc;
+  if ((rc = learned_plan(dtype, fp, w, h, &lp))) return rc;
   const int tiles_x = (w + lp.br.tw - 1) / lp.br.tw, tiles_y = (h + lp.br.th - 1) / lp.br.th;
   const long long ntiles = (long long)tiles_x * tiles_y;
   if (ntiles > 0x7fffffffLL / 64 || (long long)w * h > 0xffffffffLL) return MF_ERR_UNSUPPORTED;
@@ -753,7 +791,7 @@ int mf_learned_tile_grid(int w, int h, int dtype, const mf_footprint* fp, int* t
                          int* tiles_y, int* bracket_capacity, int* tile_w, int* tile_h) {
   if (!fp || w <= 0 || h <= 0 || (dtype != MF_U8 && dtype != MF_U16)) return MF_ERR_INVALID_ARG;
   LearnedPlan lp;
-  const int rc = learned_plan(dtype, fp, &lp);
+  const int rc = learned_plan(dtype, fp, w, h, &lp);
   if (rc) return rc;
   if (tiles_x) *tiles_x = (w + lp.br.tw - 1) / lp.br.tw;
   if (tiles_y) *tiles_y = (h + lp.br.th - 1) / lp.br.th;
