@@ -1099,37 +1099,72 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     uint32_t* pcnt = reinterpret_cast<uint32_t*>(cnt);
     constexpr int KB = KT == KEY_U8 ? 8 : 16;
     constexpr int NW = 1 << (KB - 1);   // counter words, two counters each
-    auto box_key = [&](int e, uint32_t& loc) -> uint32_t {
-      const int ly = e / a.bw, lx = e - ly * a.bw;
-      const int gx = remap(gx0 + lx, a.w, a.boundary);
-      const int gy = remap(gy0 + ly, a.h, a.boundary);
-      const long long off = (long long)gy * a.stride + gx;
-      loc = (uint32_t)((ly << 8) | lx);
-      if (KT == KEY_U8) return static_cast<const uint8_t*>(a.img)[off];
-      if (KT == KEY_U16) return static_cast<const uint16_t*>(a.img)[off];
-      return f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+    // Both passes read the box kGB elements per thread at a time (element
+    // e = e0 + j * kThreads + t, coordinates stepped as in the LDS load), the
+    // loads of a batch in flight together, then apply the batch's atomics.
+    constexpr int kGB = 8;
+    const int sx = kThreads % a.bw, sy = kThreads / a.bw;
+    auto load_batch = [&](int e0, int& lx, int& ly, uint32_t (&kk)[kGB], uint32_t (&ll)[kGB]) {
+#pragma unroll
+      for (int j = 0; j < kGB; ++j) {
+        // unconditional (remap keeps coordinates inside the image); elements
+        // numbered >= T are not used
+        const int gx = remap(gx0 + lx, a.w, a.boundary);
+        const int gy = remap(gy0 + ly, a.h, a.boundary);
+        const long long off = (long long)gy * a.stride + gx;
+        ll[j] = (uint32_t)((ly << 8) | lx);
+        if (KT == KEY_U8) kk[j] = static_cast<const uint8_t*>(a.img)[off];
+        if (KT == KEY_U16) kk[j] = static_cast<const uint16_t*>(a.img)[off];
+        if (KT == KEY_F32) kk[j] = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+        lx += sx;
+        ly += sy;
+        if (lx >= a.bw) {
+          lx -= a.bw;
+          ly += 1;
+        }
+      }
+      (void)e0;
     };
     for (int b = t; b < NW; b += kThreads) pcnt[b] = 0;
     __syncthreads();
-    for (int e = t; e < T; e += kThreads) {
-      uint32_t loc;
-      const uint32_t d = box_key(e, loc) & ((1u << KB) - 1u);
-      atomicAdd(&pcnt[d >> 1], 1u << ((d & 1u) << 4));
+    {
+      int lx = t % a.bw, ly = t / a.bw;
+      for (int e0 = 0; e0 < T; e0 += kGB * kThreads) {
+        uint32_t kk[kGB], ll[kGB];
+        load_batch(e0, lx, ly, kk, ll);
+#pragma unroll
+        for (int j = 0; j < kGB; ++j)
+          if (e0 + j * kThreads + t < T) {
+            const uint32_t d = kk[j] & ((1u << KB) - 1u);
+            atomicAdd(&pcnt[d >> 1], 1u << ((d & 1u) << 4));
+          }
+      }
     }
     __syncthreads();
     packed_exclusive_scan(pcnt, NW, wsum);
     __syncthreads();
-    for (int e = t; e < T; e += kThreads) {
-      uint32_t loc;
-      const uint32_t key = box_key(e, loc);
-      const uint32_t d = key & ((1u << KB) - 1u);
-      const uint32_t sh = (d & 1u) << 4;
-      const uint32_t slot = (atomicAdd(&pcnt[d >> 1], 1u << sh) >> sh) & 0xffffu;
-      if (KT == KEY_F32) {
-        x0[slot] = ((W)key << 16) | (W)loc;
-      } else {
-        om[slot] = (uint16_t)loc;
-        crev[slot] = (uint16_t)key;
+    {
+      int lx = t % a.bw, ly = t / a.bw;
+      for (int e0 = 0; e0 < T; e0 += kGB * kThreads) {
+        uint32_t kk[kGB], ll[kGB], slot[kGB];
+        load_batch(e0, lx, ly, kk, ll);
+#pragma unroll
+        for (int j = 0; j < kGB; ++j)
+          if (e0 + j * kThreads + t < T) {
+            const uint32_t d = kk[j] & ((1u << KB) - 1u);
+            const uint32_t sh = (d & 1u) << 4;
+            slot[j] = (atomicAdd(&pcnt[d >> 1], 1u << sh) >> sh) & 0xffffu;
+          }
+#pragma unroll
+        for (int j = 0; j < kGB; ++j)
+          if (e0 + j * kThreads + t < T) {
+            if (KT == KEY_F32) {
+              x0[slot[j]] = ((W)kk[j] << 16) | (W)ll[j];
+            } else {
+              om[slot[j]] = (uint16_t)ll[j];
+              crev[slot[j]] = (uint16_t)kk[j];
+            }
+          }
       }
     }
     __syncthreads();
@@ -1139,10 +1174,29 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   // omnigram padding: locations outside the box (box width < 256)
   if (t < 16) om[Tv + t] = 0xffff;
   if (BR && t == 16) om[0] = 0xffff;
-  // 3. ordinal image (overwrites the sort's count table)
-  for (int v = mlo + t; v < Tv; v += kThreads) {
-    const uint32_t loc = (uint32_t)om[v];
-    I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
+  // 3. ordinal image (overwrites the sort's count table); a global-scratch
+  // omnigram is read kGI entries per thread at a time, loads in flight
+  // together
+  if constexpr (GS) {
+    constexpr int kGI = 8;
+    for (int v0 = mlo; v0 < Tv; v0 += kGI * kThreads) {
+      uint32_t loc[kGI];
+#pragma unroll
+      for (int j = 0; j < kGI; ++j) {
+        const int v = v0 + j * kThreads + t;
+        loc[j] = v < Tv ? (uint32_t)om[v] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kGI; ++j) {
+        const int v = v0 + j * kThreads + t;
+        if (v < Tv) I[(int)(loc[j] >> 8) * a.pitch + (int)(loc[j] & 255u)] = (uint16_t)v;
+      }
+    }
+  } else {
+    for (int v = mlo + t; v < Tv; v += kThreads) {
+      const uint32_t loc = (uint32_t)om[v];
+      I[(int)(loc >> 8) * a.pitch + (int)(loc & 255u)] = (uint16_t)v;
+    }
   }
   if (BR) {
     // pixels outside the bracket: bit c of the masks is box pixel
