@@ -287,6 +287,11 @@ def leg_learned(torch, mf, weights, reps, check_oracle, log):
     if not os.path.exists(weights):
         return {"skipped": f"no trained weights at {os.path.relpath(weights, ROOT)}"}
     net = mf.LearnedNet.load(weights)
+    # the method without the trained network: the same network untrained (its
+    # output layer starts at the full range, so every bracket is dropped), and
+    # a constant full-range bracket for every tile
+    untrained = mf.LearnedNet(seed=4)
+    untrained.set_margin(net.margin)
     stream = torch.cuda.current_stream()
     S = 2048
     rows = []
@@ -327,10 +332,28 @@ def leg_learned(torch, mf, weights, reps, check_oracle, log):
             if check_oracle:
                 row["oracle_mismatches"] = _oracle_sample(img_np, OF.disc(r), out.cpu().numpy(),
                                                           2000, r)
+            # gain over the method without the trained network
+            out2 = torch.empty_like(img)
+            _, fbu = untrained.filter(img, fp, out=out2)
+            tu = _time_events(torch, lambda: untrained.filter(img, fp, out=out2,
+                                                              count_fallback=False), stream, reps)
+            row["untrained"] = {"ms": float(np.median(tu)), "fallback_rate": fbu / (S * S),
+                                "mismatches_vs_plain": int((out2 != ref).sum())}
+            tx, ty = mf.LearnedNet.tile_grid(S, S, mf.MF_U16, fp)
+            full = torch.tensor([0, 65535], dtype=torch.int32, device="cuda").repeat(tx * ty)
+            _, fbf = net.filter_bracketed(img, fp, full, out=out2)
+            tf = _time_events(torch, lambda: net.filter_bracketed(img, fp, full, out=out2), stream,
+                              reps)
+            row["full_range_bracket"] = {"ms": float(np.median(tf)),
+                                         "fallback_rate": fbf / (S * S),
+                                         "mismatches_vs_plain": int((out2 != ref).sum())}
             log(f"# learned {kind} r={r}: plain {row['plain_ms']:.3f} ms, learned "
-                f"{row['learned_ms']:.3f} ms, fallback {row['fallback_rate']:.4f}")
+                f"{row['learned_ms']:.3f} ms, fallback {row['fallback_rate']:.4f}; untrained "
+                f"{row['untrained']['ms']:.3f} ms (fallback {row['untrained']['fallback_rate']:.3f}),"
+                f" full-range bracket {row['full_range_bracket']['ms']:.3f} ms")
             rows.append(row)
     net.close()
+    untrained.close()
     return {"weights": os.path.relpath(weights, ROOT), "margin": net.margin,
             "size": [S, S], "dtype": "u16", "results": rows}
 

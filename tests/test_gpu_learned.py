@@ -335,3 +335,34 @@ def test_learned_full_size_sampled(mf, oracle_mod, kind):
         assert np.array_equal(got[ys, xs], exp), r
         assert 0 <= fb <= 2048 * 2048
     net.close()
+
+
+def test_trained_network_gain_over_untrained_and_full_bracket(mf, oracle_mod):
+    """What training buys, against the method without the trained network:
+    on i.i.d. uniform uint16 (the learned-proposal workload) the committed
+    network recomputes a small fraction of the pixels, while the same
+    network untrained (full-range output, every bracket dropped) and a
+    constant full-range bracket per tile send every pixel to the plain pass;
+    all three are exact."""
+    import os
+    S = 512
+    img_np = workloads.uniform(S, S, "u16", 77)
+    img = dev(img_np)
+    fp = mf.Footprint.disc(32)
+    exp = oracle_mod.filter(img_np, OF.disc(32), "clamp")
+    trained = mf.LearnedNet.load(os.path.join(os.path.dirname(mf.__file__), "weights",
+                                              "bracket_net.npz"))
+    untrained = mf.LearnedNet(seed=4)
+    untrained.set_margin(trained.margin)
+    out_t, fb_t = trained.filter(img, fp)
+    out_u, fb_u = untrained.filter(img, fp)
+    tx, ty = mf.LearnedNet.tile_grid(S, S, mf.MF_U16, fp)
+    full = torch.tensor([0, 65535], dtype=torch.int32, device="cuda").repeat(tx * ty)
+    out_f, fb_f = trained.filter_bracketed(img, fp, full)
+    torch.cuda.synchronize()
+    for o in (out_t, out_u, out_f):
+        assert np.array_equal(o.cpu().numpy(), exp)
+    assert fb_u == S * S and fb_f == S * S, (fb_u, fb_f)
+    assert fb_t <= 0.05 * S * S, fb_t
+    trained.close()
+    untrained.close()

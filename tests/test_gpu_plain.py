@@ -226,6 +226,27 @@ def test_lognormal_f32_full_size_sampled(mf, oracle_mod, name):
     assert np.array_equal(got[ys, xs].view(np.uint32), exp.view(np.uint32))
 
 
+def test_lognormal_f32_three_planes_all_windows(mf, oracle_mod):
+    """The whole float32 workload: three 3840x2160 log-normal planes with
+    +-1e6 outliers (one seeded stack), each plane filtered on its own under
+    the mirror boundary with the disc r=48, ellipse 60x20 at 30 degrees and
+    hexagon R=40 windows; 1000 seeded output pixels per plane and window
+    against the oracle."""
+    stack = workloads.lognormal_f32(3840, 2160, planes=3, seed=2)
+    wins = [(mf.Footprint.disc(48), OF.disc(48)),
+            (mf.Footprint.ellipse(60, 20, 30), OF.ellipse(60, 20, 30)),
+            (mf.Footprint.regular_polygon(6, 40), OF.regular_polygon(6, 40))]
+    for p in range(3):
+        img = stack[p]
+        rng = np.random.default_rng(100 + p)
+        xs = rng.integers(0, 3840, 1000)
+        ys = rng.integers(0, 2160, 1000)
+        for q, (fa, fb) in enumerate(wins):
+            got = run(mf, img, fa, "mirror")
+            exp = oracle_mod.filter_points(img, fb, xs, ys, "mirror")
+            assert np.array_equal(got[ys, xs].view(np.uint32), exp.view(np.uint32)), (p, q)
+
+
 @pytest.mark.parametrize("dt,r,w,h", [("u8", 123, 41, 29), ("f32", 118, 37, 23), ("u16", 110, 70, 45)])
 def test_plain_largest_windows(mf, oracle_mod, dt, r, w, h):
     """Windows up to the largest the 8-bit box coordinates allow (width 247,
