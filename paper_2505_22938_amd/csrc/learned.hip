@@ -92,17 +92,17 @@ __global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
 // the image by radix selection on the value bits: a 256-bin histogram of
 // the top byte finds the byte holding rank k, then (16-bit) a histogram of
 // the low byte among the values with that top byte.  The four waves take
-// the window's rows in turn, sixteen rows of loads in flight per wave, and
-// keep the values in LDS for the second histogram when the window has at
-// most kStage taps (larger windows are read again).  Adds the list length
-// to fail_px.
-constexpr int kSelStage = 8192, kSelMaxRows = 512;
+// the window's rows in turn, eight rows (up to 256 taps each) of loads in
+// flight per wave, and keep the values in LDS for the second histogram
+// when the window has at most kSelStage taps (larger windows are read
+// again).  Adds the list length to fail_px.
+constexpr int kSelStage = 16384, kSelMaxRows = 512;
 template <int KT>
 __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
                                                               const unsigned int* miss,
                                                               const unsigned int* miss_count,
                                                               unsigned long long* fail_px) {
-  constexpr int kRows = 16;
+  constexpr int kRows = 8;
   __shared__ uint32_t hist[256];
   __shared__ uint16_t stage[kSelStage];
   __shared__ int rowbase[kSelMaxRows + 1];   // staged position of each row's first tap
@@ -113,18 +113,23 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
   if ((int)blockIdx.x >= n) return;   // uniform per workgroup
   const int nrows = f.nrows;          // <= kSelMaxRows (host-checked)
   // rowbase = exclusive prefix sum of the row widths (wave 0, 64 rows per step)
+  __shared__ int widest;
   if (wid == 0) {
-    int carry = 0;
+    int carry = 0, wmax = 0;
     for (int r0 = 0; r0 <= nrows; r0 += 64) {
       const int r = r0 + lane;
       const int wdt = r < nrows ? f.spans[r].y - f.spans[r].x + 1 : 0;
       const int incl = (int)wave_inclusive_scan((uint32_t)wdt, lane);
       if (r <= nrows) rowbase[r] = carry + incl - wdt;
       carry += __shfl(incl, 63, 64);
+      wmax = max(wmax, wdt);
     }
+    for (int d = 32; d >= 1; d >>= 1) wmax = max(wmax, __shfl_xor(wmax, d, 64));
+    if (lane == 0) widest = wmax;
   }
   __syncthreads();
   const int N = rowbase[nrows];
+  const int nq = min(4, (widest + 63) >> 6);   // 64-tap slices of the widest row (<= 255)
   const bool staged = N <= kSelStage;
   constexpr int kPasses = KT == KEY_U8 ? 1 : 2;
   for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
@@ -142,10 +147,11 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
           if ((v >> 8) == prefix) atomicAdd(&hist[v & 255u], 1u);
         }
       } else {
-        // this wave's rows: wid, wid + 4, ...; kRows of them per batch
+        // this wave's rows: wid, wid + 4, ...; kRows of them per batch, each
+        // row read in nq slices of 64 taps, all loads of a batch in flight
         for (int b0 = wid; b0 < nrows; b0 += 4 * kRows) {
-          uint32_t v[kRows][2];
-          bool ok[kRows][2];
+          uint32_t v[kRows][4];
+          bool ok[kRows][4];
 #pragma unroll
           for (int j = 0; j < kRows; ++j) {
             const int rr = b0 + 4 * j, r = min(rr, nrows - 1);
@@ -153,40 +159,28 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
             const long long rowoff =
                 (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < 4; ++q) {
               const int dx = sp.x + lane + 64 * q;
-              ok[j][q] = rr < nrows && dx <= sp.y;
-              const int gx = remap(x + min(dx, (int)sp.y), f.w, f.boundary);
-              v[j][q] = KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
-                                     : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
+              ok[j][q] = q < nq && rr < nrows && dx <= sp.y;
+              v[j][q] = 0;
+              if (q < nq) {   // uniform
+                const int gx = remap(x + min(dx, (int)sp.y), f.w, f.boundary);
+                v[j][q] = KT == KEY_U8
+                              ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
+                              : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
+              }
             }
           }
 #pragma unroll
           for (int j = 0; j < kRows; ++j)
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < 4; ++q)
               if (ok[j][q]) {
                 const int pos = rowbase[b0 + 4 * j] + lane + 64 * q;
                 if (pass == 0 && staged) stage[pos] = (uint16_t)v[j][q];
                 if (pass == 0 || (v[j][q] >> 8) == prefix)
                   atomicAdd(&hist[(v[j][q] >> sh) & 255u], 1u);
               }
-          // rows wider than 128 taps: the rest one load at a time
-          for (int j = 0; j < kRows && b0 + 4 * j < nrows; ++j) {
-            const int r = b0 + 4 * j;
-            const short2 sp = f.spans[r];
-            const long long rowoff =
-                (long long)remap(y + f.dy_min + r, f.h, f.boundary) * f.stride;
-            for (int dx = sp.x + lane + 128; dx <= sp.y; dx += 64) {
-              const int gx = remap(x + dx, f.w, f.boundary);
-              const uint32_t vv =
-                  KT == KEY_U8 ? (uint32_t)static_cast<const uint8_t*>(f.img)[rowoff + gx]
-                               : (uint32_t)static_cast<const uint16_t*>(f.img)[rowoff + gx];
-              if (pass == 0 && staged) stage[rowbase[r] + dx - sp.x] = (uint16_t)vv;
-              if (pass == 1 && (vv >> 8) != prefix) continue;
-              atomicAdd(&hist[(vv >> sh) & 255u], 1u);
-            }
-          }
         }
       }
       __syncthreads();
