@@ -35,6 +35,8 @@ constexpr int kThreads = 1024;            // threads per tile workgroup
 constexpr int kWaves = kThreads / 64;     // wave64
 constexpr int kDigits = 16;               // 4-bit radix digits
 constexpr int kCounterBytes = kDigits * kThreads * 2;
+constexpr int kHistWords = 256;           // seed histogram bins per wave (32-bit)
+constexpr int kHistBytes = kWaves * kHistWords * 4;
 
 enum { KEY_U8 = 0, KEY_U16 = 1, KEY_F32 = 2 };
 enum { SHAPE_DISC = 0, SHAPE_SPANS = 1 };

@@ -108,7 +108,7 @@ int make_plan(int dtype, const mf_footprint* fp, int lds_max, int tw, int th, Im
   // seed histograms.
   const int TP = round_up(T, 8) + 16;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
-  const int hb = kWaves * 128 * 4;
+  const int hb = kHistBytes;
   int A;
   if (dtype == MF_F32) {
     const int kb = std::max(4 * (round_up(T, 4) + 4), ib);   // keys, then the ordinal image
@@ -140,7 +140,7 @@ int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   if (rc) return rc;
   const int T = d->T;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
-  const int hb = kWaves * 128 * 4;
+  const int hb = kHistBytes;
   const int B = std::max(kCounterBytes, ib + hb);
   const int tb = table_bytes(d);
   // region A: TPc 32-bit words (candidate exchange), afterwards omega and C
@@ -184,7 +184,7 @@ int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   const int T = d->T;
   const int TP = round_up(T, 8) + 16;
   const int ib = round_up(2 * d->pitch * d->bh, 16);
-  const int hb = kWaves * 128 * 4;
+  const int hb = kHistBytes;
   const int B0 = std::max(kCounterBytes, ib + hb);
   // slot: float keys: x0 and x1, TP 64-bit words each, x0 holding C32 +
   // omega after the sort; 8/16-bit keys: omega (u16) + C16 only

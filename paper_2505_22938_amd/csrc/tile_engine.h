@@ -336,12 +336,12 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
                                           int& esc_c) {
   const int lane = threadIdx.x & 63;
   int zeros = 0;
-  // 256 bins of 16-bit counts, two per word (a window has < 65536 taps).
-  // Bracketed tiles: pixels below the bracket (ordinal 0) are counted in a
-  // register and pixels above it (0xffff) skipped, so the histogram holds
-  // only in-bracket ordinals and no bin is hammered by atomics.
-  hist[lane * 2] = 0;
-  hist[lane * 2 + 1] = 0;
+  // 256 bins of 32-bit counts (a bin's word address is the ordinal shifted,
+  // no packing arithmetic per update).  Bracketed tiles: pixels below the
+  // bracket (ordinal 0) are counted in a register and pixels above it
+  // (0xffff) skipped, so the histogram holds only in-bracket ordinals and no
+  // bin is hammered by atomics.
+  reinterpret_cast<uint4*>(hist)[lane] = make_uint4(0u, 0u, 0u, 0u);
   wave_lds_sync();
   // one footprint row per lane; eight ordinals read before their eight
   // histogram updates, so the reads overlap instead of each waiting behind
@@ -361,8 +361,7 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
           zeros += iv[j] == 0;
           if (iv[j] == 0 || iv[j] == 0xffffu) continue;
         }
-        const uint32_t b = iv[j] >> hshift;
-        atomicAdd(&hist[b >> 1], 1u << ((b & 1u) << 4));
+        atomicAdd(&hist[iv[j] >> hshift], 1u);
       }
     }
   }
@@ -375,8 +374,8 @@ __device__ __forceinline__ int seed_solve(int cx, int cy, int T, int hshift, int
     esc_c = zeros;
     return -1;
   }
-  const uint32_t w0 = hist[lane * 2], w1 = hist[lane * 2 + 1];
-  uint32_t h[4] = {w0 & 0xffffu, w0 >> 16, w1 & 0xffffu, w1 >> 16};
+  const uint4 hw = reinterpret_cast<const uint4*>(hist)[lane];
+  uint32_t h[4] = {hw.x, hw.y, hw.z, hw.w};
   const uint32_t sum = h[0] + h[1] + h[2] + h[3];
   uint32_t cum = wave_inclusive_scan(sum, lane) - sum;
   int bin = -1;
@@ -485,7 +484,9 @@ __device__ __forceinline__ int row_select(bool act, int p, int c, int k, uint32_
       const int n = need - before;
       cand = up ? qj + nth_bit8(bits, n) : qj + nth_bit8(bits, pc - 1 - n);
     }
-    cand = row_max16(cand);
+    // (the row's candidate reaches its lanes only on an iteration where some
+    // row finds its member)
+    if (wave_ballot(!done && need < tot) != 0) cand = row_max16(cand);
     if (!done) {
       if (need < tot) {
         res = cand;
@@ -1227,7 +1228,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     hshift = 0;
     while (((Tv - 1) >> hshift) > 255) ++hshift;
   }
-  uint32_t* hist = hist_all + wid * 128;
+  uint32_t* hist = hist_all + wid * kHistWords;
   int blocks = 0, seeds = 0, seed_taps = 0, groups = 0;
   long long seed_clk = 0, row_clk = 0, sweep_clk = 0;
   const int tw = a.tw, segs = a.segs, R = a.band_rows;

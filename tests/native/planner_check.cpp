@@ -52,7 +52,7 @@ void check_plan(const mf::ImageDesc& d, int dtype, int lds_max, bool br) {
   const int T = d.T;
   const int TP = ru(T, 8) + 16;
   const int ib = ru(2 * d.pitch * d.bh, 16);
-  const int hb = mf::kWaves * 128 * 4;
+  const int hb = mf::kHistBytes;
   const int nr4 = ru(d.nrows, 4);
   const int tab = 128 + 12 * nr4 + 16 * d.ncols;
   const long long L = d.lds_bytes;

@@ -63,16 +63,25 @@ def test_forced_fallback_wrong_brackets(mf, net, oracle_mod, dtype):
     assert fb == int((exp != 0).sum())   # every pixel whose median is not 0
 
 
-def test_full_bracket_no_fallback(mf, net, oracle_mod):
+@pytest.mark.parametrize("shape", ["ellipse", "disc3"])
+def test_full_bracket_fallback_by_capacity(mf, net, oracle_mod, shape):
+    """A full-range bracket holds every box pixel: tiles run bracketed (no
+    fallback) when the box fits the bracketed layout's capacity, and go to
+    the plain pass whole otherwise; the output is exact either way."""
     img = workloads.natural_u16(257, 131, seed=3)
-    fp = mf.Footprint.ellipse(9, 4, 20)
+    if shape == "ellipse":
+        fp, ofp = mf.Footprint.ellipse(9, 4, 20), OF.ellipse(9, 4, 20)
+    else:
+        fp, ofp = mf.Footprint.disc(3), OF.disc(3)
     tx, ty, tw, th = tile_info(mf, 257, 131, mf.MF_U16, fp)
+    cap = mf.LearnedNet.tile_grid(257, 131, mf.MF_U16, fp, with_capacity=True)[2]
+    box = (tw + fp.dx_max - fp.dx_min) * (th + fp.dy_max - fp.dy_min)
     br = np.zeros((ty * tx, 2))
     br[:, 1] = 65535
     out, fb = net.filter_bracketed(dev(img), fp, brackets_dev(br), boundary="mirror")
     torch.cuda.synchronize()
-    assert fb == 0
-    assert np.array_equal(out.cpu().numpy(), oracle_mod.filter(img, OF.ellipse(9, 4, 20), "mirror"))
+    assert fb == (0 if box <= cap else 257 * 131), (box, cap, fb)
+    assert np.array_equal(out.cpu().numpy(), oracle_mod.filter(img, ofp, "mirror"))
 
 
 def box_counts(img, r, tx, ty, tw, th, br):
