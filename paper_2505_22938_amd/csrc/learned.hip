@@ -504,6 +504,7 @@ int learned_plan(int dtype, const mf_footprint* fp, int w, int h, LearnedPlan* l
 int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int h,
                      size_t stride, int dtype, const mf_footprint* fp, int boundary, void* out,
                      unsigned long long* fallback_px, hipStream_t s, const LearnedPlan& lp) {
+  if (lp.fb.nrows > mf::kSelMaxRows) return MF_ERR_UNSUPPORTED;   // (boxes are <= 256 tall)
   const void* table = nullptr;
   int rc = mf::footprint_device_table(fp, lp.dev, &table, s);
   if (rc) return rc;
@@ -543,7 +544,6 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
                      n->tile_fail);
   hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
                      (const int*)n->tile_fail, n->fail_px, lp.ratio);
-  if (f.nrows > mf::kSelMaxRows) return MF_ERR_UNSUPPORTED;
   const long long pgrid = std::max(1, lp.di.cus) * 8LL;   // 8 pixels at a time per CU
   if (dtype == MF_U8)
     hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,
