@@ -150,13 +150,12 @@ int make_plan_br(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   int cap = (avail / 4) - 32;
   cap = std::min(cap, std::min(T, 17 * kThreads));
   if (cap < kThreads) return MF_ERR_UNSUPPORTED;
-  // Region A capped at what fits in half the LDS, where that still holds an
-  // eighth of the box: a bracket holding more of the box saves little of
-  // the sort, and its tile goes to the plain pass right after the load
-  // instead of ranking most of its box twice (on smooth images most tiles
-  // are such); a tight bracket holds far fewer pixels.
-  const int cap2 = ((lds_max / 2 - B - tb) / 4) - 32;
-  if (cap2 >= std::max(kThreads, T / 8)) cap = std::min(cap, cap2);
+  // Region A capped at a quarter of the box: a bracket holding more of the
+  // box saves less than three quarters of the sort, and its tile goes to the
+  // plain pass right after the load instead of ranking most of its box
+  // twice (on smooth images most tiles are such); a tight bracket holds far
+  // fewer pixels (about a tenth of the box on i.i.d. input).
+  cap = std::min(cap, std::max(kThreads, T / 4));
   const int TPc = round_up(cap + 1, 8) + 16;
   d->off_p = 0;
   d->off_C = 2 * TPc;
