@@ -375,3 +375,38 @@ def test_trained_network_gain_over_untrained_and_full_bracket(mf, oracle_mod):
     assert fb_t <= 0.05 * S * S, fb_t
     trained.close()
     untrained.close()
+
+
+def test_failed_tiles_recomputed_on_the_plain_plan(mf, net, oracle_mod):
+    """Failed bracketed tiles are recomputed on the plain filter's own tile
+    plan when its tiles split them evenly (here 64x64 plain tiles under
+    64x128 bracketed tiles): every other bracketed tile gets an empty
+    bracket (it fails), the rest a full-range one; the output equals the
+    plain filter's bit for bit and the fallback count is the failed tiles'
+    pixels."""
+    W = H = 2048
+    img_np = workloads.natural_u16(W, H, seed=9)
+    img = dev(img_np)
+    fp = mf.Footprint.disc(16)
+    tw, th = mf.LearnedNet.tile_shape(W, H, mf.MF_U16, fp)
+    plain = mf.query_plan(W, H, mf.MF_U16, fp)
+    assert plain["tile_w"] == tw and th % plain["tile_h"] == 0 and th > plain["tile_h"], (
+        (tw, th), plain)
+    tx, ty = mf.LearnedNet.tile_grid(W, H, mf.MF_U16, fp)
+    br = np.zeros((tx * ty, 2))
+    br[:, 1] = 65535
+    fail = (np.arange(tx * ty) % 2) == 1
+    br[fail, 0] = 1          # lo > hi: no bracket, the tile fails
+    br[fail, 1] = 0
+    out, fb = net.filter_bracketed(img, fp, brackets_dev(br))
+    ref = mf.median_filter(img, fp, "clamp")
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    cap = mf.LearnedNet.tile_grid(W, H, mf.MF_U16, fp, with_capacity=True)[2]
+    box = (tw + fp.dx_max - fp.dx_min) * (th + fp.dy_max - fp.dy_min)
+    expect = int(fail.sum()) * tw * th if box <= cap else W * H
+    assert fb == expect, (fb, expect, box, cap)
+    rng = np.random.default_rng(5)
+    xs, ys = rng.integers(0, W, 1000), rng.integers(0, H, 1000)
+    assert np.array_equal(out.cpu().numpy()[ys, xs],
+                          oracle_mod.filter_points(img_np, OF.disc(16), xs, ys, "clamp"))
