@@ -879,6 +879,23 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     build_tables(a.spans, a.nrows, a.ncols, a.dx_min, a.dy_min);
   }
 
+  // Box pixels that no window of the tile reaches (the corners of the
+  // rounded rectangle the windows sweep; disc windows: farther than the
+  // radius from every window centre of the tile) take the largest key, so
+  // they rank above every pixel a window holds and the omnigram walks
+  // between medians do not cross them (no window counts them, so the
+  // results are unchanged).  Not for chained tiles, whose ranked box is
+  // carried into the next tile, where these rows hold window pixels, nor
+  // for passes with a window per plane.
+  constexpr uint32_t kTopKey = KT == KEY_U8 ? 0xffu : KT == KEY_U16 ? 0xffffu : 0xffffffffu;
+  const bool cut = SHAPE == SHAPE_DISC && !CHAIN && !BR && !(GEN && a.multi_fp);
+  const int ccx0 = -a.dx_min, ccx1 = -a.dx_min + a.tw - 1;   // window centres, box coordinates
+  const int ccy0 = -a.dy_min, ccy1 = -a.dy_min + a.th - 1;
+  auto corner_cut = [&](int lx, int ly) -> bool {
+    if (!cut) return false;
+    const int ox = max(0, max(ccx0 - lx, lx - ccx1)), oy = max(0, max(ccy0 - ly, ly - ccy1));
+    return ox * ox + oy * oy > a.limit;
+  };
   uint64_t below_bits = 0, above_bits = 0;   // BR: classes of this thread's chunks
   if constexpr (BR) {
     static_assert(KT != KEY_F32, "bracketed tiles take 8/16-bit keys");
@@ -1052,6 +1069,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
             kk = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
             q = p;
           }
+          if (corner_cut(lx, ly)) kk = KT == KEY_F32 ? kTopKey : ((kTopKey << 16) | p);
         }
         key[i] = e < T ? kk : 0u;
         pos[i] = (uint16_t)q;
@@ -1117,6 +1135,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
         if (KT == KEY_U8) kk[j] = static_cast<const uint8_t*>(a.img)[off];
         if (KT == KEY_U16) kk[j] = static_cast<const uint16_t*>(a.img)[off];
         if (KT == KEY_F32) kk[j] = f32_to_key(static_cast<const uint32_t*>(a.img)[off]);
+        if (corner_cut(lx, ly)) kk[j] = kTopKey;
         lx += sx;
         ly += sy;
         if (lx >= a.bw) {
