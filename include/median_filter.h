@@ -120,8 +120,9 @@ void mf_footprint_destroy(mf_footprint* fp);
  * table (kept until mf_footprint_destroy).  Large windows (global-scratch
  * tiles) use a scratch buffer cached per (device, stream), allocated on first
  * need and replaced by a larger one when a later call on that stream needs
- * more (about 0.3-1 MB per concurrent tile: 130 MB for radius 100 uint16,
- * twice that for float32); mf_release_scratch frees it.
+ * more (2 bytes per box pixel and concurrent tile for 8/16-bit images, 8
+ * for float32: 33 MB for radius 100 uint16, 133 MB for float32);
+ * mf_release_scratch frees it.
  *
  * Graph capture: while `stream` is being captured the call never allocates.
  * It returns MF_ERR_UNSUPPORTED instead if the footprint's table is not yet

@@ -185,18 +185,18 @@ int make_plan_gs(int dtype, const mf_footprint* fp, int lds_max, int tw, int th,
   const int ib = round_up(2 * d->pitch * d->bh, 16);
   const int hb = kHistBytes;
   const int B0 = std::max(kCounterBytes, ib + hb);
-  // slot: float keys: x0 and x1, TP 64-bit words each, x0 holding C32 +
-  // omega after the sort; 8/16-bit keys: omega (u16) + C16 only
-  const int wb = dtype == MF_F32 ? 8 : 4;
-  // region B also holds the sort's packed 16-bit key counters (2^16 of
-  // them for 16-bit and float keys, 2^8 for 8-bit keys)
+  // slot: 8/16-bit keys: the omnigram (TP u16 entries), written by the
+  // counting pass.  Float keys: x0 and x1, TP 32-bit words each, for the
+  // stable passes over the high key bits; the last pass writes the omnigram
+  // over x0.  The output is read back from the image (no reverse map).
+  // Region B also holds the sort's packed 16-bit key counters (2^16 of
+  // them for 16-bit and float keys, 2^8 for 8-bit keys).
   const int B = std::max(B0, dtype == MF_U8 ? 512 : 131072);
-  d->off_p = 4 * TP;
-  d->off_C = dtype == MF_F32 ? 0 : 2 * TP;
-  // (8/16-bit keys need only the omnigram and C16, 4 * TP bytes)
-  d->off_x1 = wb * TP;
+  d->off_p = 0;
+  d->off_C = 0;
+  d->off_x1 = 4 * TP;
   d->off_lr = 0;
-  d->slot_bytes = round_up(dtype == MF_F32 ? 2 * wb * TP : 4 * TP, 256);
+  d->slot_bytes = round_up(dtype == MF_F32 ? 8 * TP : 2 * TP, 256);
   d->ipt = (T + kThreads - 1) / kThreads;
   d->off_B = 0;
   d->off_I = 0;

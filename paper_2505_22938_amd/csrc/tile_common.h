@@ -245,13 +245,11 @@ __device__ __forceinline__ void bucket_pass(const uint32_t (&key)[ITEMS],
 }
 
 // Stable LSD radix sort of T elements in global memory, for boxes whose
-// sort exchange does not fit in LDS.  Elements are words (key << 16 |
-// location), 32-bit for 8/16-bit keys and 64-bit for 32-bit keys; the
-// passes sort bits [shift0, shift0 + 4*passes).  Pass p reads xa (p even)
-// or xb (p odd) and writes the other; the last pass writes neither but
-// splits each word into its location (omega[]) and key (crev16[] for
-// 16-bit keys, else crev32[]), which may alias the buffer that pass does
-// not read.
+// sort exchange does not fit in LDS.  Elements are 32-bit words (key bits
+// << 16 | location); the passes sort bits [shift0, shift0 + 4*passes).
+// Pass p reads xa (p even) or xb (p odd) and writes the other; the last
+// pass writes neither but only each word's location, to omega[], which may
+// alias the buffer that pass does not read.
 //
 // Element e is visited by thread e % kThreads in chunk e / kThreads, so
 // every load is coalesced.  The stable rank of an element is the scanned
@@ -266,17 +264,15 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
          ((d & 8u) ? b3 : ~b3);
 }
 
-template <typename W>
-__device__ __forceinline__ void global_radix_sort(W* xa, W* xb, int T, int shift0, int passes,
-                                                  uint16_t* omega, uint16_t* crev16,
-                                                  uint32_t* crev32, uint16_t* cnt,
+__device__ __forceinline__ void global_radix_sort(uint32_t* xa, uint32_t* xb, int T, int shift0,
+                                                  int passes, uint16_t* omega, uint16_t* cnt,
                                                   uint32_t* wsum) {
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int nchunks = (T + kThreads - 1) / kThreads;
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int pass = 0; pass < passes; ++pass) {
-    const W* src = (pass & 1) ? xb : xa;
-    W* dst = (pass & 1) ? xa : xb;
+    const uint32_t* src = (pass & 1) ? xb : xa;
+    uint32_t* dst = (pass & 1) ? xa : xb;
     const int sh = shift0 + 4 * pass;
     const bool last = pass + 1 == passes;
     // zero the counters (16 entries per thread)
@@ -289,7 +285,7 @@ __device__ __forceinline__ void global_radix_sort(W* xa, W* xb, int T, int shift
     for (int c = 0; c < nchunks; ++c) {
       const int e = c * kThreads + t;
       const bool valid = e < T;
-      const W v = valid ? src[e] : (W)0;
+      const uint32_t v = valid ? src[e] : 0u;
       const uint32_t d = (uint32_t)(v >> sh) & 15u;
       const uint64_t peers = digit_peers(d, valid);
       if (valid && (peers & ~lt) == (1ull << lane))   // highest lane of its digit group
@@ -320,84 +316,47 @@ __device__ __forceinline__ void global_radix_sort(W* xa, W* xb, int T, int shift
     for (int c = 0; c < nchunks; ++c) {
       const int e = c * kThreads + t;
       const bool valid = e < T;
-      const W v = valid ? src[e] : (W)0;
+      const uint32_t v = valid ? src[e] : 0u;
       const uint32_t d = (uint32_t)(v >> sh) & 15u;
       const uint64_t peers = digit_peers(d, valid);
       if (valid) {
         const uint32_t o =
             (uint32_t)cnt[(d * nchunks + c) * kWaves + wid] + (uint32_t)__popcll(peers & lt);
-        if (!last) {
-          dst[o] = v;
-        } else {
-          omega[o] = (uint16_t)v;
-          if (crev32) crev32[o] = (uint32_t)(v >> 16);
-          else crev16[o] = (uint16_t)(v >> 16);
-        }
+        if (!last) dst[o] = v;
+        else omega[o] = (uint16_t)v;
       }
     }
     __syncthreads();
   }
 }
 
-// Global-memory form of bucket_pass: one counting pass over `bits` (<= 12)
-// key bits at bit `sh` of the words in src, without keeping the order of
-// equal digits (LDS atomics count the buckets and then hand out slots), the
-// words scattered to dst.  cnt: 1 << bits LDS words.
-template <typename W>
-__device__ __forceinline__ void global_bucket_pass(const W* src, W* dst, int T, int sh, int bits,
-                                                   uint32_t* cnt, uint32_t* wsum) {
-  const int t = threadIdx.x;
-  const uint32_t mask = (1u << bits) - 1u;
-  const int nb = 1 << bits;
-  for (int b = t; b < nb; b += kThreads) cnt[b] = 0;
-  __syncthreads();
-  for (int e = t; e < T; e += kThreads) atomicAdd(&cnt[(uint32_t)(src[e] >> sh) & mask], 1u);
-  __syncthreads();
-  {
-    uint32_t c[4] = {0, 0, 0, 0};
-    const bool own = 4 * t < nb;
-    if (own) {
-      const uint4 v = reinterpret_cast<const uint4*>(cnt)[t];
-      c[0] = v.x;
-      c[1] = v.y;
-      c[2] = v.z;
-      c[3] = v.w;
-    }
-    const uint32_t sum = c[0] + c[1] + c[2] + c[3];
-    const uint32_t base = block_exclusive_scan(sum, wsum);
-    if (own)
-      reinterpret_cast<uint4*>(cnt)[t] =
-          make_uint4(base, base + c[0], base + c[0] + c[1], base + c[0] + c[1] + c[2]);
-  }
-  __syncthreads();
-  for (int e = t; e < T; e += kThreads) {
-    const W v = src[e];
-    dst[atomicAdd(&cnt[(uint32_t)(v >> sh) & mask], 1u)] = v;
-  }
-  __syncthreads();
-}
-
 // Exclusive scan, in place, over the 2 * nw 16-bit counters packed two per
 // word in w (counter 2i in the low half of word i); the totals stay below
-// 65536.  Thread t scans a contiguous run of words.  Contains barriers.
+// 65536.  Wave v owns the contiguous run of words [v * per, (v + 1) * per)
+// and walks it 64 words at a time, lane l on word l of each step, so every
+// LDS access of a step falls in its own bank (a run per thread would put
+// all lanes of a wave on two banks).  Contains barriers.
 __device__ __forceinline__ void packed_exclusive_scan(uint32_t* w, int nw, uint32_t* wsum) {
-  const int t = threadIdx.x;
-  const int per = (nw + kThreads - 1) / kThreads;
-  const int w0 = t * per;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int per = (nw + kWaves - 1) / kWaves;
+  const int w0 = wid * per, w1 = min(w0 + per, nw);
   uint32_t sum = 0;
-  for (int i = 0; i < per; ++i)
-    if (w0 + i < nw) {
-      const uint32_t v = w[w0 + i];
-      sum += (v & 0xffffu) + (v >> 16);
-    }
-  uint32_t base = block_exclusive_scan(sum, wsum);
-  for (int i = 0; i < per; ++i)
-    if (w0 + i < nw) {
-      const uint32_t v = w[w0 + i];
-      const uint32_t lo = v & 0xffffu;
-      w[w0 + i] = base | ((base + lo) << 16);
-      base += lo + (v >> 16);
-    }
+  for (int i = w0 + lane; i < w1; i += 64) {
+    const uint32_t v = w[i];
+    sum += (v & 0xffffu) + (v >> 16);
+  }
+  // the runs before this wave's: the exclusive prefix of one value per wave
+  const uint32_t tot = __shfl(wave_inclusive_scan(sum, lane), 63, 64);
+  uint32_t run = block_exclusive_scan(lane == 63 ? tot : 0u, wsum);
+  for (int i0 = w0; i0 < w1; i0 += 64) {
+    const int i = i0 + lane;
+    const uint32_t v = i < w1 ? w[i] : 0u;
+    const uint32_t lo = v & 0xffffu, s = lo + (v >> 16);
+    const uint32_t incl = wave_inclusive_scan(s, lane);
+    const uint32_t b = run + incl - s;
+    if (i < w1) w[i] = b | ((b + lo) << 16);
+    run += __shfl(incl, 63, 64);
+  }
 }
 
 }  // namespace mf

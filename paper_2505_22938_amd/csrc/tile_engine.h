@@ -825,7 +825,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
   uint16_t* crev = reinterpret_cast<uint16_t*>(abase + a.off_C);      // u8/u16 reverse map
   uint16_t* cnt = reinterpret_cast<uint16_t*>(smem + a.off_B);
   uint16_t* I = reinterpret_cast<uint16_t*>(smem + a.off_I);
-  constexpr bool GATHER = !GS && !BR;   // no reverse map in LDS (store_out)
+  constexpr bool GATHER = !BR;   // no reverse map kept (store_out)
   uint32_t* hist_all = reinterpret_cast<uint32_t*>(smem + a.off_hist);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + a.off_tab);
   const int nr4 = (a.nrows + 3) & ~3;
@@ -1108,13 +1108,13 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     // LDS atomics on packed 16-bit counters, the counters are scanned, and
     // each pixel is read again and claims the next slot of its key value.
     // Ties take their slots in any order, which the ordinal transform
-    // allows, so 8/16-bit keys are fully sorted: the omnigram and the
-    // reverse map are written directly.  Float keys go to global scratch
-    // as (key << 16 | location) words for four stable 4-bit passes over
-    // the high 16 bits.
-    using W = typename std::conditional<KT == KEY_F32, uint64_t, uint32_t>::type;
-    W* x0 = reinterpret_cast<W*>(gslot);
-    W* x1 = reinterpret_cast<W*>(gslot + a.off_x1);
+    // allows, so 8/16-bit keys are fully sorted: each slot receives just
+    // the pixel's location, the omnigram entry (the output is read back
+    // from the image, so no reverse map is kept).  Float keys go to x0 as
+    // (high 16 key bits << 16 | location) words for four stable 4-bit
+    // passes over the high bits.
+    uint32_t* x0 = reinterpret_cast<uint32_t*>(gslot);
+    uint32_t* x1 = reinterpret_cast<uint32_t*>(gslot + a.off_x1);
     uint32_t* pcnt = reinterpret_cast<uint32_t*>(cnt);
     constexpr int KB = KT == KEY_U8 ? 8 : 16;
     constexpr int NW = 1 << (KB - 1);   // counter words, two counters each
@@ -1178,17 +1178,13 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
 #pragma unroll
         for (int j = 0; j < kGB; ++j)
           if (e0 + j * kThreads + t < T) {
-            if (KT == KEY_F32) {
-              x0[slot[j]] = ((W)kk[j] << 16) | (W)ll[j];
-            } else {
-              om[slot[j]] = (uint16_t)ll[j];
-              crev[slot[j]] = (uint16_t)kk[j];
-            }
+            if (KT == KEY_F32) x0[slot[j]] = (kk[j] & 0xffff0000u) | ll[j];
+            else om[slot[j]] = (uint16_t)ll[j];
           }
       }
     }
     __syncthreads();
-    if (KT == KEY_F32) global_radix_sort<W>(x0, x1, T, 32, 4, om, nullptr, kbuf, cnt, wsum);
+    if (KT == KEY_F32) global_radix_sort(x0, x1, T, 16, 4, om, cnt, wsum);
   }
   if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)

@@ -92,19 +92,17 @@ void check_plan(const mf::ImageDesc& d, int dtype, int lds_max, bool br) {
     disjoint({pcnt, tables}, L, d, dtype, "sort");
     disjoint({counters, tables}, L, d, dtype, "sort");
     if (dtype == MF_F32) {
-      const Reg x0{"scratch x0", 0, 8LL * TP};
-      const Reg x1{"scratch x1", d.off_x1, (long long)d.off_x1 + 8LL * TP};
+      const Reg x0{"scratch x0", 0, 4LL * TP};
+      const Reg x1{"scratch x1", d.off_x1, (long long)d.off_x1 + 4LL * TP};
       disjoint({x0, x1}, S, d, dtype, "scratch sort");
-      // the last stable pass reads x1 and writes C32 and the omnigram in x0
+      // the last stable pass reads x1 and writes the omnigram in x0
       const Reg om{"scratch omnigram", d.off_p, (long long)d.off_p + 2LL * TP};
-      const Reg crev{"scratch reverse map", 0, 4LL * TP};
-      disjoint({om, crev, x1}, S, d, dtype, "scratch bands");
-      if (om.hi > x0.hi || crev.hi > x0.hi) fail("omnigram/reverse map beyond x0", d, dtype);
+      disjoint({om, x1}, S, d, dtype, "scratch bands");
+      if (om.lo < x0.lo || om.hi > x0.hi) fail("omnigram outside x0", d, dtype);
     } else {
-      // the counting pass writes the omnigram and C16 directly
+      // the counting pass writes the omnigram directly
       const Reg om{"scratch omnigram", 0, 2LL * TP};
-      const Reg crev{"scratch reverse map", d.off_C, (long long)d.off_C + 2LL * TP};
-      disjoint({om, crev}, S, d, dtype, "scratch sort and bands");
+      disjoint({om}, S, d, dtype, "scratch sort and bands");
     }
     const Reg I{"ordinal image", d.off_I, (long long)d.off_I + ib};
     disjoint({I, hist, tables}, L, d, dtype, "bands");
