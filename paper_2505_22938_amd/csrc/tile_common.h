@@ -246,84 +246,74 @@ __device__ __forceinline__ void bucket_pass(const uint32_t (&key)[ITEMS],
 
 // Stable LSD radix sort of T elements in global memory, for boxes whose
 // sort exchange does not fit in LDS.  Elements are 32-bit words (key bits
-// << 16 | location); the passes sort bits [shift0, shift0 + 4*passes).
-// Pass p reads xa (p even) or xb (p odd) and writes the other; the last
-// pass writes neither but only each word's location, to omega[], which may
-// alias the buffer that pass does not read.
+// << 16 | location); the passes sort bits [shift0, shift0 + 8*passes), 8 at
+// a time.  Pass p reads xa (p even) or xb (p odd) and writes the other; the
+// last pass writes neither but only each word's location, to omega[], which
+// may alias the buffer that pass does not read.
 //
-// Element e is visited by thread e % kThreads in chunk e / kThreads, so
-// every load is coalesced.  The stable rank of an element is the scanned
-// count of its digit over (chunk, wave) groups in element order plus its
-// rank among the lanes of its wave holding the same digit (four ballots).
-// Counters: cnt[(digit * nchunks + chunk) * kWaves + wave], u16; T <= 65535
-// and nchunks <= 64 keep them within 16 * 64 * kWaves entries.
-__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
-  const uint64_t b0 = __ballot(d & 1u), b1 = __ballot(d & 2u), b2 = __ballot(d & 4u),
-                 b3 = __ballot(d & 8u), bv = __ballot(valid);
-  return bv & ((d & 1u) ? b0 : ~b0) & ((d & 2u) ? b1 : ~b1) & ((d & 4u) ? b2 : ~b2) &
-         ((d & 8u) ? b3 : ~b3);
+// Wave v owns the contiguous elements [v*S, (v+1)*S) and walks them 64 at a
+// time in order (coalesced loads).  A pass counts digits per (digit, wave),
+// scans the counters digit-major, then walks again: an element's slot is its
+// (digit, wave) counter plus its rank among the lanes of its step holding
+// the same digit (eight ballots), and the highest such lane advances the
+// counter, so equal digits keep their order.  Counters: cw[wave * 257 +
+// digit] (the odd row pitch spreads a wave's digits and a scan thread's
+// waves over the banks), 16 * 257 LDS words.
+__device__ __forceinline__ uint64_t digit_peers8(uint32_t d, bool valid) {
+  uint64_t p = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t m = __ballot((d >> b) & 1u);
+    p &= ((d >> b) & 1u) ? m : ~m;
+  }
+  return p;
 }
 
 __device__ __forceinline__ void global_radix_sort(uint32_t* xa, uint32_t* xb, int T, int shift0,
-                                                  int passes, uint16_t* omega, uint16_t* cnt,
+                                                  int passes, uint16_t* omega, uint32_t* cw,
                                                   uint32_t* wsum) {
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-  const int nchunks = (T + kThreads - 1) / kThreads;
+  constexpr int kPitch = 257;
+  const int S = (((T + kWaves - 1) / kWaves) + 63) & ~63;
+  const int e0 = wid * S, e1 = min(e0 + S, T);
   const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t* mine = cw + wid * kPitch;
   for (int pass = 0; pass < passes; ++pass) {
     const uint32_t* src = (pass & 1) ? xb : xa;
     uint32_t* dst = (pass & 1) ? xa : xb;
-    const int sh = shift0 + 4 * pass;
+    const int sh = shift0 + 8 * pass;
     const bool last = pass + 1 == passes;
-    // zero the counters (16 entries per thread)
-    {
-      uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
-      row[0] = make_uint4(0, 0, 0, 0);
-      row[1] = make_uint4(0, 0, 0, 0);
-    }
+    for (int i = t; i < kWaves * kPitch; i += kThreads) cw[i] = 0;
     __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-      const int e = c * kThreads + t;
-      const bool valid = e < T;
-      const uint32_t v = valid ? src[e] : 0u;
-      const uint32_t d = (uint32_t)(v >> sh) & 15u;
-      const uint64_t peers = digit_peers(d, valid);
-      if (valid && (peers & ~lt) == (1ull << lane))   // highest lane of its digit group
-        cnt[(d * nchunks + c) * kWaves + wid] = (uint16_t)__popcll(peers);
-    }
+    for (int e = e0 + lane; e < e1; e += 64) atomicAdd(&mine[(src[e] >> sh) & 255u], 1u);
     __syncthreads();
     {
-      uint4* row = reinterpret_cast<uint4*>(cnt + 16 * t);
-      uint4 a = row[0], b = row[1];
-      uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-      uint32_t run = 0, ex[16];
+      // thread t scans entries 4t .. 4t + 3 of the digit-major order
+      // (digit t / 4, waves 4 (t % 4) .. 4 (t % 4) + 3)
+      const int d = t >> 2, w0 = (t & 3) * 4;
+      uint32_t c[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t lo = w[j] & 0xffffu, hi = w[j] >> 16;
-        ex[2 * j] = run;
-        run += lo;
-        ex[2 * j + 1] = run;
-        run += hi;
+      for (int j = 0; j < 4; ++j) c[j] = cw[(w0 + j) * kPitch + d];
+      uint32_t b = block_exclusive_scan(c[0] + c[1] + c[2] + c[3], wsum);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        cw[(w0 + j) * kPitch + d] = b;
+        b += c[j];
       }
-      const uint32_t base = block_exclusive_scan(run, wsum);
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        w[j] = ((ex[2 * j] + base) & 0xffffu) | ((ex[2 * j + 1] + base) << 16);
-      row[0] = make_uint4(w[0], w[1], w[2], w[3]);
-      row[1] = make_uint4(w[4], w[5], w[6], w[7]);
     }
     __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-      const int e = c * kThreads + t;
-      const bool valid = e < T;
+    for (int c0 = e0; c0 < e1; c0 += 64) {
+      const int e = c0 + lane;
+      const bool valid = e < e1;
       const uint32_t v = valid ? src[e] : 0u;
-      const uint32_t d = (uint32_t)(v >> sh) & 15u;
-      const uint64_t peers = digit_peers(d, valid);
+      const uint32_t d = (v >> sh) & 255u;
+      const uint64_t peers = digit_peers8(d, valid);
+      const uint32_t base = valid ? mine[d] : 0u;
       if (valid) {
-        const uint32_t o =
-            (uint32_t)cnt[(d * nchunks + c) * kWaves + wid] + (uint32_t)__popcll(peers & lt);
+        const uint32_t o = base + (uint32_t)__popcll(peers & lt);
         if (!last) dst[o] = v;
         else omega[o] = (uint16_t)v;
+        if ((peers & ~lt) == (1ull << lane)) mine[d] = base + (uint32_t)__popcll(peers);
       }
     }
     __syncthreads();

@@ -1111,7 +1111,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
     // allows, so 8/16-bit keys are fully sorted: each slot receives just
     // the pixel's location, the omnigram entry (the output is read back
     // from the image, so no reverse map is kept).  Float keys go to x0 as
-    // (high 16 key bits << 16 | location) words for four stable 4-bit
+    // (high 16 key bits << 16 | location) words for two stable 8-bit
     // passes over the high bits.
     uint32_t* x0 = reinterpret_cast<uint32_t*>(gslot);
     uint32_t* x1 = reinterpret_cast<uint32_t*>(gslot + a.off_x1);
@@ -1184,7 +1184,7 @@ __device__ __forceinline__ bool tile_body(const D& a, int tile, unsigned char* s
       }
     }
     __syncthreads();
-    if (KT == KEY_F32) global_radix_sort(x0, x1, T, 16, 4, om, cnt, wsum);
+    if (KT == KEY_F32) global_radix_sort(x0, x1, T, 16, 2, om, pcnt, wsum);
   }
   if (a.counters && t == 0) atomicAdd(&a.counters[CNT_SORTED], (unsigned long long)(Tv - mlo));
   // omnigram padding: locations outside the box (box width < 256)

@@ -90,7 +90,8 @@ void check_plan(const mf::ImageDesc& d, int dtype, int lds_max, bool br) {
     const long long pc = dtype == MF_U8 ? 512 : 131072;
     const Reg pcnt{"packed key counters", d.off_B, (long long)d.off_B + pc};
     disjoint({pcnt, tables}, L, d, dtype, "sort");
-    disjoint({counters, tables}, L, d, dtype, "sort");
+    const Reg dcnt{"stable-pass digit counters", d.off_B, (long long)d.off_B + 4LL * 16 * 257};
+    disjoint({dcnt, tables}, L, d, dtype, "sort");
     if (dtype == MF_F32) {
       const Reg x0{"scratch x0", 0, 4LL * TP};
       const Reg x1{"scratch x1", d.off_x1, (long long)d.off_x1 + 4LL * TP};
