@@ -270,14 +270,18 @@ static int default_th_cap(const mf_footprint* fp) {
 }
 
 // The first LDS shape that fits (widest, then tallest first, heights up to
-// th_cap), unless a global-scratch shape re-reads far fewer box pixels per
-// output pixel (small LDS tiles under large windows).  Measured crossover:
-// the global-scratch plan wins once the LDS plan's amplification is about
-// twice as high (4096^2 uint16: radius 52-60 run 11-30 % faster in LDS
-// tiles up to that ratio, radius 64 is 18 % faster in global scratch; float
-// keys, 64-bit words and 8 passes, cross over at the same ratio).  fill_tiles > 0: among 64-wide shapes, step down in height (not
-// below 64) while the image would have fewer tiles than that (fewer tiles
-// per CU than needed to balance tiles of uneven cost).
+// th_cap), unless a global-scratch shape re-reads enough fewer box pixels
+// per output pixel (small LDS tiles under large windows).  Measured
+// crossover, as the ratio of the LDS plan's amplification to the
+// global-scratch plan's: about 1.25 for 8/16-bit keys (4096^2 uint16 disc:
+// radius 48, ratio 1.14, 1.91 ms in LDS against 2.06; radius 52, 1.27,
+// 2.22 against 2.19; radius 56, 1.47, 2.56 against 2.33; radius 60, 3.15
+// against 2.42) and about 1.7 for float keys, whose global-scratch sort
+// has two more passes (3840x2160 float32 disc: radius 40, ratio 1.5, 1.07
+// against 1.29 ms; radius 44, 1.68, 1.38 against 1.40).  fill_tiles > 0:
+// a kept 64-wide LDS shape steps down in height (not below 64) while the
+// image would have fewer tiles than that (fewer tiles per CU than needed
+// to balance tiles of uneven cost).
 static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax_cap, int th_cap,
                         int w, int h, long long fill_tiles, ImageDesc* d) {
   ImageDesc gs{};
@@ -285,12 +289,15 @@ static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax
   auto finish = [&](ImageDesc* c) {
     const double amp = (double)c->T / ((double)c->tw * c->th);
     const double amp_gs = have_gs ? (double)gs.T / ((double)gs.tw * gs.th) : 1e300;
-    if (amp > 2.0 * amp_gs) *c = gs;
+    if (amp > (dtype == MF_F32 ? 1.7 : 1.25) * amp_gs) *c = gs;
     return MF_OK;
   };
-  // 64 wide, heights in steps of 16
+  // 64 wide, heights in steps of 16 (the tallest that fits is weighed
+  // against the global-scratch plan before any step down)
   for (int th = th_cap; th >= 16; th -= 16) {
     if (make_plan(dtype, fp, lds_max, 64, th, d) != MF_OK || d->imax > imax_cap) continue;
+    finish(d);
+    if (d->gs) return MF_OK;
     if (fill_tiles > 0) {
       for (int t2 = th - 16; t2 >= 64; t2 -= 16) {
         const long long tiles = (long long)((w + 63) / 64) * ((h + d->th - 1) / d->th);
@@ -299,7 +306,7 @@ static int default_plan(int dtype, const mf_footprint* fp, int lds_max, int imax
         if (make_plan(dtype, fp, lds_max, 64, t2, &c) == MF_OK && c.imax <= imax_cap) *d = c;
       }
     }
-    return finish(d);
+    return MF_OK;
   }
   // narrower tiles for windows whose 64-wide boxes do not fit
   static const int tws[] = {32, 16, 8};

@@ -173,15 +173,21 @@ def test_tile_override_validation_and_general_shapes():
 
 def test_large_window_plans_minimise_amplification():
     """Radius 100: the box of a 54x56 tile (254x256) is the largest that fits
-    the 8-bit box coordinates; LDS tiles up to twice the global-scratch
-    plan's amplification (radius 48: 64x96, radius 56: 64x64), tall
-    global-scratch tiles beyond (radius 64)."""
+    the 8-bit box coordinates; LDS tiles up to 1.25 times the global-scratch
+    plan's amplification for 8/16-bit keys (radius 48: 64x96 LDS, ratio
+    1.14; radius 56: 64x128 global scratch, ratio 1.47) and 1.7 times for
+    float keys (radius 44: 64x48 LDS, ratio 1.68), tall global-scratch tiles
+    beyond (radius 64)."""
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(100))
     assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (54, 56, 254, 256)
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(48))
     assert (p["tile_w"], p["tile_h"]) == (64, 96), p
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(56))
-    assert (p["tile_w"], p["tile_h"]) == (64, 64), p
+    assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (64, 128, 176, 240), p
+    p = mf.query_plan(3840, 2160, mf.MF_F32, mf.Footprint.disc(44))
+    assert (p["tile_w"], p["tile_h"]) == (64, 48), p
+    p = mf.query_plan(3840, 2160, mf.MF_F32, mf.Footprint.disc(48))
+    assert (p["tile_w"], p["tile_h"], p["box_w"], p["box_h"]) == (64, 128, 160, 224), p
     p = mf.query_plan(4096, 4096, mf.MF_U16, mf.Footprint.disc(64))
     # a box whose 4-byte sort words exceed the LDS: the global-scratch plan
     assert p["tile_w"] * p["tile_h"] >= 64 * 96 and p["box_w"] * p["box_h"] * 4 > 160 * 1024, p
