@@ -153,6 +153,29 @@ def test_plain_global_scratch_radius(mf, oracle_mod, r, dtype):
     assert_same(got, oracle_mod.filter(img, OF.disc(r), "mirror"), f"{dtype} r={r}")
 
 
+@pytest.mark.parametrize("case", ["one_high_half", "three_octaves_signed"])
+def test_global_scratch_f32_order_of_high_halves(mf, oracle_mod, case):
+    """Float keys in global scratch are ranked by a counting pass over their
+    low 16 bits and then stable passes over the high 16 bits.  Inputs whose
+    pixels share few high halves but differ in the low ones make every
+    median depend on both orders: one high half for all pixels (values in
+    [1, 1 + 2^-7)), and three octaves of both signs with low bits drawn at
+    random (so equal high halves are common and their low halves decide)."""
+    rng = np.random.default_rng(5)
+    w, h = 210, 170
+    if case == "one_high_half":
+        img = (1.0 + rng.random((h, w)) * (2.0 ** -7)).astype(np.float32)
+    else:
+        hi = rng.choice(np.array([0x3F80, 0x4000, 0x4080, 0xBF80, 0xC000], np.uint32), (h, w))
+        img = ((hi << 16) | rng.integers(0, 1 << 16, (h, w), dtype=np.uint32)).view(np.float32)
+    fp = mf.Footprint.disc(64)
+    p = mf.query_plan(w, h, mf.MF_F32, fp)
+    assert p["box_w"] * p["box_h"] * 8 > 160 * 1024, p   # a global-scratch plan
+    for boundary in ("clamp", "mirror"):
+        assert_same(run(mf, img, fp, boundary), oracle_mod.filter(img, OF.disc(64), boundary),
+                    f"{case} {boundary}")
+
+
 @pytest.mark.parametrize("name", ["disc48", "ellipse", "hexagon"])
 def test_lognormal_f32_footprints(mf, oracle_mod, name):
     # float32 planes with +-1e6 outliers under the mirror boundary
