@@ -29,12 +29,15 @@ __global__ __launch_bounds__(kThreads) void mf_general_kernel(ImageDesc a) {
 template <int KT, int SHAPE>
 __global__ __launch_bounds__(kThreads) void mf_general_gs_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int claimed;
   unsigned char* slot = a.scratch + (long long)blockIdx.x * a.slot_bytes;
   const int ntiles = a.tiles_x * a.tiles_y;
-  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-    tile_body<KT, SHAPE, 1, true, false, true>(a, xcd_tile(v, ntiles), smem, slot);
+  int run = 0;
+  for (int tile; (tile = claim_tile(a.claim, ntiles, run, &claimed)) >= 0;) {
+    tile_body<KT, SHAPE, 1, true, false, true>(a, tile, smem, slot);
     __syncthreads();
   }
+  claim_done(a.claim);
 }
 
 namespace {

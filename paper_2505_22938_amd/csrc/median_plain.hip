@@ -27,16 +27,20 @@ __global__ __launch_bounds__(kThreads) void mf_plain_kernel(ImageDesc a) {
   tile_body<KT, SHAPE, IMAX, false>(a, xcd_tile(blockIdx.x, gridDim.x), smem, nullptr);
 }
 
-// Large boxes: a persistent grid, one global scratch slot per workgroup.
+// Large boxes: a persistent grid, one global scratch slot per workgroup,
+// tiles claimed at run time.
 template <int KT, int SHAPE>
 __global__ __launch_bounds__(kThreads) void mf_plain_gs_kernel(ImageDesc a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int claimed;
   unsigned char* slot = a.scratch + (long long)blockIdx.x * a.slot_bytes;
   const int ntiles = a.tiles_x * a.tiles_y;
-  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-    tile_body<KT, SHAPE, 1, true>(a, xcd_tile(v, ntiles), smem, slot);
+  int run = 0;
+  for (int tile; (tile = claim_tile(a.claim, ntiles, run, &claimed)) >= 0;) {
+    tile_body<KT, SHAPE, 1, true>(a, tile, smem, slot);
     __syncthreads();
   }
+  claim_done(a.claim);
 }
 
 // Chained tiles: workgroup (x, c) walks tiles c * S .. c * S + S - 1 of
@@ -128,16 +132,19 @@ int launch_with_plan(ImageDesc a, int dev, const DeviceInfo& di, hipStream_t str
     const int occ = std::max(1, std::min(2, di.lds_max / std::max(1, a.lds_bytes)));
     grid = std::min<long long>(ntiles, (long long)di.cus * occ);
     if (ext_scratch) {
-      const long long fit = (long long)(ext_bytes / (size_t)a.slot_bytes);
+      // claim words first (zero-initialised, left zero by every launch)
+      if (ext_bytes < (size_t)kClaimBytes) return MF_ERR_SCRATCH_LIMIT;
+      const long long fit = (long long)((ext_bytes - kClaimBytes) / (size_t)a.slot_bytes);
       if (fit < 1) return MF_ERR_SCRATCH_LIMIT;
       grid = std::min(grid, fit);
-      a.scratch = ext_scratch;
+      a.scratch = ext_scratch + kClaimBytes;
     } else {
       void* scr = nullptr;
       const int rc = get_scratch(dev, stream, (size_t)grid * (size_t)a.slot_bytes, &scr);
       if (rc) return rc;
       a.scratch = static_cast<unsigned char*>(scr);
     }
+    a.claim = reinterpret_cast<unsigned int*>(a.scratch - kClaimBytes);
   }
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kThreads), a.lds_bytes, stream, a);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;

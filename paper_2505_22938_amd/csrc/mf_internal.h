@@ -68,9 +68,11 @@ struct ImageDesc {
   // LDS layout, bytes (off_I: the ordinal image)
   int off_p, off_C, off_B, off_I, off_hist, off_tab, lds_bytes;
   unsigned long long* counters;  // optional work counters (null: off)
-  // global-scratch variant: per-workgroup slot of slot_bytes at scratch
+  // global-scratch variant: per-workgroup slot of slot_bytes at scratch;
+  // claim: the persistent grid's tile-claim words (zero between launches)
   unsigned char* scratch;
   long long slot_bytes;
+  unsigned int* claim;
   int off_x1, off_lr, ipt;
   // kernel selection: key type, shape, 1 = global-scratch variant, and the
   // register capacity (elements per thread) of the LDS variant
@@ -135,7 +137,11 @@ int validate_image(const void* img, int w, int h, size_t stride_bytes, int dtype
 
 // Global scratch cached per (device, stream); never allocates while the
 // stream is capturing (MF_ERR_UNSUPPORTED instead).  release_scratch frees
-// every cached buffer (mf_release_scratch).
+// every cached buffer (mf_release_scratch).  *out points to `bytes` of slot
+// space; the kClaimBytes before it hold the tile-claim words (nine used),
+// zeroed when the buffer is allocated and left zero by every launch that
+// uses them.
+constexpr int kClaimBytes = 256;
 int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out);
 int release_scratch();
 

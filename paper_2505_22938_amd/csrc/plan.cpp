@@ -437,19 +437,24 @@ int get_scratch(int dev, hipStream_t stream, size_t bytes, void** out) {
         e.ptr = nullptr;
         e.bytes = 0;
         e.captured = false;
-        if (hipMalloc(&e.ptr, bytes) != hipSuccess) return MF_ERR_NOMEM;
+        if (hipMalloc(&e.ptr, kClaimBytes + bytes) != hipSuccess) return MF_ERR_NOMEM;
+        if (hipMemsetAsync(e.ptr, 0, kClaimBytes, stream) != hipSuccess) return MF_ERR_HIP;
         e.bytes = bytes;
       }
       e.captured = e.captured || capturing;
-      *out = e.ptr;
+      *out = static_cast<unsigned char*>(e.ptr) + kClaimBytes;
       return MF_OK;
     }
   }
   if (capturing) return MF_ERR_UNSUPPORTED;
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return MF_ERR_NOMEM;
+  if (hipMalloc(&p, kClaimBytes + bytes) != hipSuccess) return MF_ERR_NOMEM;
+  if (hipMemsetAsync(p, 0, kClaimBytes, stream) != hipSuccess) {
+    (void)hipFree(p);
+    return MF_ERR_HIP;
+  }
   g_scratch.push_back({dev, stream, p, bytes, false});
-  *out = p;
+  *out = static_cast<unsigned char*>(p) + kClaimBytes;
   return MF_OK;
 }
 

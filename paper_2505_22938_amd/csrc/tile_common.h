@@ -19,6 +19,38 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
 }
 
+// Persistent grids claim their tiles at run time, so a workgroup whose
+// tiles were cheap goes on to take more.  The tiles are cut into kXcd
+// contiguous runs as xcd_tile cuts them; workgroup b takes tiles from run
+// b % kXcd (the XCD it runs on) until that run is used up, then from the
+// following runs.  claim[x] counts the claims made on run x (claims past
+// its end included) and claim[kXcd] the workgroups done; the last
+// workgroup to finish clears them, so every launch starts from zeros.
+// `run` starts at 0 and is the workgroup's position in its order of runs;
+// `sh` is one LDS word.  Returns the next tile, or -1 when every run is
+// used up.  Contains barriers: call from all threads.
+__device__ __forceinline__ int claim_tile(unsigned int* claim, int ntiles, int& run, int* sh) {
+  constexpr int kXcd = 8;
+  const int q = ntiles / kXcd, rem = ntiles % kXcd;
+  while (run < kXcd) {
+    const int x = ((int)blockIdx.x + run) % kXcd;
+    if (threadIdx.x == 0) *sh = (int)atomicAdd(&claim[x], 1u);
+    __syncthreads();
+    const int j = *sh;
+    __syncthreads();
+    if (j < q + (x < rem ? 1 : 0)) return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + j;
+    ++run;
+  }
+  return -1;
+}
+__device__ __forceinline__ void claim_done(unsigned int* claim) {
+  constexpr int kXcd = 8;
+  if (threadIdx.x == 0 && atomicAdd(&claim[kXcd], 1u) == gridDim.x - 1) {
+#pragma unroll
+    for (int i = 0; i <= kXcd; ++i) atomicExch(&claim[i], 0u);
+  }
+}
+
 // Boundary rule: clamp repeats the edge pixel; mirror reflects about it
 // without repeating it and folds with period 2(n-1).
 __device__ __forceinline__ int remap(int x, int n, int boundary) {
