@@ -182,14 +182,14 @@ def _time_events(torch, fn, stream, reps):
     return [a.elapsed_time(b) for a, b in ev]
 
 
-def _oracle_sample(img_np, ofp, got, n, seed):
+def _oracle_sample(img_np, ofp, got, n, seed, boundary="clamp"):
     """Mismatches of `got` against the oracle at n random pixels."""
     import oracle
     h, w = img_np.shape
     rng = np.random.default_rng(seed)
     xs = rng.integers(0, w, n)
     ys = rng.integers(0, h, n)
-    exp = oracle.filter_points(img_np, ofp, xs, ys, "clamp", nthreads=oracle.default_threads())
+    exp = oracle.filter_points(img_np, ofp, xs, ys, boundary, nthreads=oracle.default_threads())
     a = got[ys, xs]
     if a.dtype == np.float32:
         return int((a.view(np.uint32) != exp.view(np.uint32)).sum())
@@ -484,6 +484,76 @@ def _windows_case(torch, mf, img, img_np, reps, check_oracle, log, fps, ofps, na
     return res
 
 
+def leg_configs(torch, mf, img, img_np, reps, check_oracle, log):
+    """The plain filter on the other workloads it is specified on: the
+    256x256 uint8 i.i.d. image under a radius-4 disc (checked in full); the
+    headline image at radii 8 and 100 (radius 32 is the headline); the
+    3-channel 3840x2160 float32 log-normal image, channels filtered
+    independently, under each of its three windows (mirror)."""
+    import workloads
+    from oracle import footprints as OF
+    stream = torch.cuda.current_stream()
+    res = {}
+    u8 = workloads.plain_u8(256, 256, 0)
+    d8 = torch.from_numpy(u8).cuda()
+    o8 = torch.empty_like(d8)
+    fp = mf.Footprint.disc(4)
+    mf.median_filter(d8, fp, "clamp", out=o8)
+    ms = float(np.median(_time_events(
+        torch, lambda: mf.median_filter(d8, fp, "clamp", out=o8), stream, reps)))
+    r = {"image": "256x256 uint8 i.i.d. uniform, seed 0", "window": "disc r=4 (49 taps)",
+         "boundary": "clamp", "ms": ms, "mpx_s": 256 * 256 / 1e3 / ms}
+    if check_oracle:
+        import oracle
+        exp = oracle.filter(u8, OF.disc(4), "clamp", nthreads=oracle.default_threads())
+        r["oracle_mismatches"] = int((o8.cpu().numpy() != exp).sum())
+        r["oracle_checked_px"] = 256 * 256
+    res["u8_256_disc4"] = r
+    log(f"# configs: 256^2 u8 disc 4 {ms:.3f} ms")
+    h, w = img_np.shape
+    out = torch.empty_like(img)
+    for rad in (8, 100):
+        fp = mf.Footprint.disc(rad)
+        mf.median_filter(img, fp, "clamp", out=out)
+        ms = float(np.median(_time_events(
+            torch, lambda: mf.median_filter(img, fp, "clamp", out=out), stream, reps)))
+        r = {"image": f"{w}x{h} uint16 natural-like (the headline image)",
+             "window": f"disc r={rad} ({fp.taps} taps)", "boundary": "clamp", "ms": ms,
+             "mpx_s": w * h / 1e3 / ms, "plan": mf.query_plan(w, h, mf.MF_U16, fp)}
+        if check_oracle:
+            r["oracle_mismatches"] = _oracle_sample(img_np, OF.disc(rad), out.cpu().numpy(),
+                                                    1000, 40 + rad)
+            r["oracle_checked_px"] = 1000
+        res[f"u16_{w}_disc{rad}"] = r
+        log(f"# configs: {w}^2 u16 disc {rad} {ms:.3f} ms")
+    f32 = workloads.lognormal_f32(3840, 2160, planes=3, seed=2)
+    planes = [torch.from_numpy(np.ascontiguousarray(p)).cuda() for p in f32]
+    outs = [torch.empty_like(p) for p in planes]
+    for name, fp, ofp in (("disc r=48", mf.Footprint.disc(48), OF.disc(48)),
+                          ("ellipse 60x20 @30", mf.Footprint.ellipse(60, 20, 30),
+                           OF.ellipse(60, 20, 30)),
+                          ("hexagon R=40", mf.Footprint.regular_polygon(6, 40),
+                           OF.regular_polygon(6, 40))):
+        def run():
+            for p, o in zip(planes, outs):
+                mf.median_filter(p, fp, "mirror", out=o)
+
+        run()
+        ms = float(np.median(_time_events(torch, run, stream, reps)))
+        r = {"image": "3840x2160x3 float32 log-normal (mu 0, sigma 1) with 2% +-1e6 outliers, "
+                      "seed 2, channels filtered independently",
+             "window": f"{name} ({fp.taps} taps)", "boundary": "mirror", "ms_3_channels": ms,
+             "mpx_s": 3 * 3840 * 2160 / 1e3 / ms}
+        if check_oracle:
+            r["oracle_mismatches"] = sum(
+                _oracle_sample(f32[c], ofp, outs[c].cpu().numpy(), 300, 60 + c, "mirror")
+                for c in range(3))
+            r["oracle_checked_px"] = 900
+        res[f"f32_3840x2160x3_{name.split()[0]}"] = r
+        log(f"# configs: 3840x2160x3 f32 {name} {ms:.3f} ms (3 channels)")
+    return res
+
+
 def leg_stress(torch, mf, reps, check_oracle, log):
     """1024x1024 uint16 0/65535 checkerboard inside a mid-grey frame, disc
     r=32: the input the paper's limitations discussion describes as slow
@@ -522,7 +592,7 @@ def main():
     ap.add_argument("--radius", type=int, default=32)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--legs", default="plain,batched,learned,ranks,windows,stress")
+    ap.add_argument("--legs", default="plain,configs,batched,learned,ranks,windows,stress")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2505_22938_amd", "weights",
                                                       "bracket_net.npz"))
     ap.add_argument("--copy-check", action="store_true")
@@ -622,6 +692,8 @@ def main():
     learned = (leg_learned(torch, mf, args.weights, 5, not args.no_cpu, log)
                if "learned" in legs else None)
     stress = leg_stress(torch, mf, 5, not args.no_cpu, log) if "stress" in legs else None
+    configs = (leg_configs(torch, mf, img, img_np, 5, not args.no_cpu, log)
+               if "configs" in legs else None)
     # last: the batched leg records autotuned tile shapes, which every later
     # plan in this process would use instead of the default ones
     batched = (leg_batched(torch, mf, 5, not args.no_cpu, log, autotune=not args.no_autotune)
@@ -675,6 +747,7 @@ def main():
                    "lds_bytes": plan["lds_bytes"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "configs": configs,
         "batched": batched,
         "learned": learned,
         "ranks": ranks,
