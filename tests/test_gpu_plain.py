@@ -304,6 +304,43 @@ def test_autotune_records_shape_and_cache_round_trip(mf, oracle_mod, tmp_path):
             mf.query_plan(300, 210, mf.MF_U16, fp)["tile_h"]) == (tw, th)
 
 
+def test_global_scratch_on_two_streams(mf, oracle_mod):
+    """Global-scratch tiles are claimed at run time through counters kept
+    with each stream's scratch: calls queued on two streams without
+    synchronising in between, and a graph of such a call replayed on its
+    stream, all stay exact."""
+    a = workloads.natural_u16(230, 170, seed=41)
+    b = workloads.uniform(190, 210, "u16", 42)
+    fp = mf.Footprint.disc(64)
+    exp_a = oracle_mod.filter(a, OF.disc(64), "clamp")
+    exp_b = oracle_mod.filter(b, OF.disc(64), "mirror")
+    da, db = to_dev(a), to_dev(b)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs_a = [torch.empty_like(da) for _ in range(3)]
+    outs_b = [torch.empty_like(db) for _ in range(3)]
+    for i in range(3):
+        with torch.cuda.stream(s1):
+            mf.median_filter(da, fp, "clamp", out=outs_a[i])
+        with torch.cuda.stream(s2):
+            mf.median_filter(db, fp, "mirror", out=outs_b[i])
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert_same(outs_a[i].cpu().numpy(), exp_a, f"stream 1 call {i}")
+        assert_same(outs_b[i].cpu().numpy(), exp_b, f"stream 2 call {i}")
+    g = torch.cuda.CUDAGraph()
+    out_g = torch.empty_like(da)
+    with torch.cuda.graph(g, stream=s1):
+        mf.median_filter(da, fp, "clamp", out=out_g)
+    for rep in range(3):
+        out_g.zero_()
+        g.replay()
+        with torch.cuda.stream(s2):
+            mf.median_filter(db, fp, "mirror", out=outs_b[0])
+        torch.cuda.synchronize()
+        assert_same(out_g.cpu().numpy(), exp_a, f"replay {rep}")
+        assert_same(outs_b[0].cpu().numpy(), exp_b, f"stream 2 beside replay {rep}")
+
+
 def test_graph_capture_after_warm_call_and_release(mf, oracle_mod):
     """A plain call is captured into a graph once one uncaptured call on the
     same stream has uploaded its footprint and sized its scratch (radius 100:
