@@ -94,17 +94,21 @@ __global__ __launch_bounds__(kThreads) void mf_fallback_gs_kernel(ImageDesc f,
 // the low byte among the values with that top byte.  The four waves take
 // the window's rows in turn, eight rows (up to 256 taps each) of loads in
 // flight per wave, and keep the values in LDS for the second histogram
-// when the window has at most kSelStage taps (larger windows are read
-// again).  Adds the list length to fail_px.
+// when the window fits the staging buffer (the launch's dynamic LDS of
+// stage_cap taps, which the host sizes to the window when it has at most
+// kSelStage taps, else empty: the window is then read again).  Sized to the
+// window, the buffer leaves room for more workgroups per CU under small
+// windows.  Adds the list length to fail_px.
 constexpr int kSelStage = 16384, kSelMaxRows = 512;
 template <int KT>
 __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
                                                               const unsigned int* miss,
                                                               const unsigned int* miss_count,
-                                                              unsigned long long* fail_px) {
+                                                              unsigned long long* fail_px,
+                                                              int stage_cap) {
   constexpr int kRows = 8;
   __shared__ uint32_t hist[256];
-  __shared__ uint16_t stage[kSelStage];
+  extern __shared__ __attribute__((aligned(16))) uint16_t stage[];   // stage_cap entries
   __shared__ int rowbase[kSelMaxRows + 1];   // staged position of each row's first tap
   __shared__ int sel[2];                     // bin holding rank k, count below the bin
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void mf_pixel_select_kernel(ImageDesc f,
   __syncthreads();
   const int N = rowbase[nrows];
   const int nq = min(4, (widest + 63) >> 6);   // 64-tap slices of the widest row (<= 255)
-  const bool staged = N <= kSelStage;
+  const bool staged = N <= stage_cap;
   constexpr int kPasses = KT == KEY_U8 ? 1 : 2;
   for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
     const uint32_t idx = miss[i];
@@ -545,14 +549,18 @@ int bracketed_filter(mf_learned* n, const uint2* br, const void* img, int w, int
   hipLaunchKernelGGL(fk, dim3((unsigned)fgrid), dim3(mf::kThreads), f.lds_bytes, s, f,
                      (const int*)n->tile_fail, n->fail_px, lp.ratio);
   const long long pgrid = std::max(1, lp.di.cus) * 8LL;   // 8 pixels at a time per CU
+  // staging buffer: the window's taps (the kernel stages windows of at most
+  // kSelStage taps)
+  const int stage_cap = fp->taps <= mf::kSelStage ? fp->taps : 0;
+  const size_t stage_bytes = (size_t)stage_cap * 2;
   if (dtype == MF_U8)
-    hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256), 0,
-                       s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,
-                       n->fail_px);
+    hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U8>, dim3((unsigned)pgrid), dim3(256),
+                       stage_bytes, s, f, (const unsigned int*)n->miss,
+                       (const unsigned int*)n->miss_count, n->fail_px, stage_cap);
   else
     hipLaunchKernelGGL(mf::mf_pixel_select_kernel<mf::KEY_U16>, dim3((unsigned)pgrid), dim3(256),
-                       0, s, f, (const unsigned int*)n->miss, (const unsigned int*)n->miss_count,
-                       n->fail_px);
+                       stage_bytes, s, f, (const unsigned int*)n->miss,
+                       (const unsigned int*)n->miss_count, n->fail_px, stage_cap);
   if (hipGetLastError() != hipSuccess) return MF_ERR_HIP;
   if (fallback_px) {
     if (hipMemcpyAsync(fallback_px, n->fail_px, sizeof(unsigned long long), hipMemcpyDeviceToHost,
