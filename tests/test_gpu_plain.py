@@ -197,6 +197,15 @@ def test_natural_u16_4096_sampled(mf, oracle_mod, r):
     assert_same(got[ys, xs], exp, f"4096 r={r}")
 
 
+def test_natural_u16_4096_disc8_every_pixel(mf, oracle_mod):
+    """The 4096^2 natural-like image at radius 8, every output pixel against
+    the oracle (radius 32, the headline, is checked in full by the
+    benchmark's CPU leg)."""
+    img = workloads.natural_u16(4096, 4096, seed=1)
+    got = run(mf, img, mf.Footprint.disc(8), "clamp")
+    assert_same(got, oracle_mod.filter(img, OF.disc(8), "clamp"), "4096 r=8, all pixels")
+
+
 @pytest.mark.parametrize("dtype,fpname,tile", [
     ("u16", "disc8", (40, 24)),      # width not dividing 64, last band shorter
     ("u8", "ellipse", (48, 20)),
